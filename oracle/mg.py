@@ -1,0 +1,136 @@
+"""hp-multigrid V-cycle with the cell-wise red-black SSOR smoother (oracle).
+
+Test infrastructure only.  Follows Sec. 3 of the paper:
+  * hierarchy (Sec. 3 opening): the finest mesh carries p, p-1, ..., 1, then
+    the mesh is coarsened with p = 1; every level has its own active set,
+    surrogate faces, shifts and re-discretised operator (Sec. 4.3);
+  * smoother (Sec. 3.1): successive subspace correction over the cell
+    subspaces, u <- u + omega R_i^T A_i^{-1} R_i (f - A u), with A_i the
+    diagonal cell block, used as a symmetric (SSOR) sweep;
+  * transfers (Sec. 3.2): prolongation = embedding on the background mesh
+    (fine nodes take the coarse polynomial's value), restriction = transpose.
+
+Readings (listed in the design notes):
+  * coarsening: halve n while n is even and n/2 >= coarse_min (3);
+  * the smoother visits the two colours (i+j+k mod 2) in the order 0,1,1,0 per
+    step; cells of one colour do not couple, so a colour is updated at once;
+  * omega = 1 for p <= 2 and 0.8 for p = 3 on every level;
+  * V(1,1), a pre-smoothing step starting from zero;
+  * inactive DoFs are identically zero: restriction into an inactive coarse
+    cell is dropped, prolongation from an inactive parent gives zero;
+  * coarse solver: a direct solve with the dense matrix of the coarsest level.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from . import basis, dg
+
+
+def level_shapes(n, p, coarse_min=3):
+    """(n, p) of every level, finest first."""
+    out = [(n, q) for q in range(p, 0, -1)]
+    while n % 2 == 0 and n // 2 >= coarse_min:
+        n //= 2
+        out.append((n, 1))
+    return out
+
+
+def default_omega(p):
+    return 0.8 if p >= 3 else 1.0
+
+
+class Hierarchy:
+    def __init__(self, geom, d, n, p, coarse_min=3, omega=None, nu_pre=1, nu_post=1, **kw):
+        shapes = level_shapes(n, p, coarse_min)[::-1]          # coarsest first
+        self.levels = [dg.Level(geom, d, nn, pp, **kw) for nn, pp in shapes]
+        self.d = d
+        self.omega = default_omega(p) if omega is None else float(omega)
+        self.nu_pre, self.nu_post = nu_pre, nu_post
+        self.inv = [self._block_inverses(L) for L in self.levels]
+        self.P = [None] + [self._prolongation(self.levels[l - 1], self.levels[l])
+                           for l in range(1, len(self.levels))]
+        A0 = self.levels[0].A.toarray()
+        self.A0inv = np.linalg.inv(A0) if A0.size else A0
+        self.learned = None   # optional (omega_K, U_K, V_K) on the finest level
+
+    @staticmethod
+    def _block_inverses(L):
+        """B_K = D_K^{-1} by LU with partial pivoting (LAPACK getrf/getri)."""
+        if L.n_act == 0:
+            return np.zeros((0, L.N, L.N))
+        return np.linalg.inv(L.D)
+
+    @staticmethod
+    def _prolongation(Lc, Lf):
+        """Embedding of the coarse DG space into the fine one on the background mesh."""
+        d = Lf.d
+        nodes_f = basis.gll_nodes(Lf.p)
+        mi_f = basis.multi_indices(Lf.p + 1, d)
+        ref_f = nodes_f[mi_f]                                   # fine nodes, fine reference coords
+        rows, cols, vals = [], [], []
+        ratio = Lf.n // Lc.n                                    # 1 (p-level) or 2 (h-level)
+        for K in range(Lf.n_act):
+            mi = Lf.cells[K]
+            parent = mi // ratio
+            pc = Lc.cell_of[Lc.lin_index(parent)[0]]
+            if pc < 0:
+                continue
+            off = mi - parent * ratio
+            xc = (off[None, :] + ref_f) / ratio                 # fine nodes in coarse reference coords
+            Phi, _ = basis.tabulate(Lc.p, xc)                    # (Nf, Nc)
+            r = K * Lf.N + np.arange(Lf.N)
+            c = pc * Lc.N + np.arange(Lc.N)
+            rows.append(np.repeat(r, Lc.N))
+            cols.append(np.tile(c, Lf.N))
+            vals.append(Phi.reshape(-1))
+        if not rows:
+            return sp.csr_matrix((Lf.n_dofs, Lc.n_dofs))
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                             shape=(Lf.n_dofs, Lc.n_dofs))
+
+    # ------------------------------------------------------------ smoother
+    def colour_update(self, l, z, b, c):
+        """z_K += omega B_K (b - A z)_K for every active cell K of colour c."""
+        L = self.levels[l]
+        r = (b - L.A @ z).reshape(L.n_act, L.N)
+        zz = z.reshape(L.n_act, L.N)
+        cells = np.arange(L.n_col0) if c == 0 else np.arange(L.n_col0, L.n_act)
+        corr = self.omega * np.einsum('kij,kj->ki', self.inv[l][cells], r[cells])
+        if self.learned is not None and l == len(self.levels) - 1:
+            w, U, V, idx = self.learned                     # per boundary cell of the finest level
+            pos = -np.ones(L.n_act, dtype=np.int64)
+            pos[idx] = np.arange(len(idx))
+            sel = pos[cells] >= 0
+            kk = cells[sel]
+            j = pos[kk]
+            Br = np.einsum('kij,kj->ki', self.inv[l][kk], r[kk])
+            UVr = np.einsum('kia,kja,kj->ki', U[j], V[j], r[kk])
+            corr[sel] = (self.omega * w[j])[:, None] * (Br + UVr)
+        zz[cells] += corr
+        return z
+
+    def ssor_step(self, l, z, b):
+        for c in (0, 1, 1, 0):
+            z = self.colour_update(l, z, b, c)
+        return z
+
+    # ------------------------------------------------------------ V-cycle
+    def vcycle(self, b, l=None):
+        if l is None:
+            l = len(self.levels) - 1
+        if l == 0:
+            return self.A0inv @ b if b.size else b.copy()
+        L = self.levels[l]
+        z = np.zeros_like(b)
+        for _ in range(self.nu_pre):
+            z = self.ssor_step(l, z, b)
+        r = b - L.A @ z
+        zc = self.vcycle(self.P[l].T @ r, l - 1)
+        z = z + self.P[l] @ zc
+        for _ in range(self.nu_post):
+            z = self.ssor_step(l, z, b)
+        return z
+
+    @property
+    def fine(self):
+        return self.levels[-1]

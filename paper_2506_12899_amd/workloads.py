@@ -1,0 +1,142 @@
+"""Seeded synthetic workloads shared by the tests, the benchmark and the oracle checks.
+
+This module holds only inputs: geometries, manufactured solutions and seeded
+random vectors.  It contains none of the method's arithmetic and imports
+nothing from the library or from the oracle, so both sides can be fed from it.
+
+The five named problems mirror the paper's studies (unit disk / sphere and a
+non-trivial 2D shape, p = 1..3, 2D and 3D, Sec. 5) at the sizes of the
+performance study:
+
+  disk32_q1     2D, 32^2 cells, Q1, disk r = 0.7, u = sin(pi x) sin(pi y)
+  star512_q2    2D, 512^2 cells, Q2, star r(t) = 0.6 + 0.15 sin(5 t), u = exp(x) cos(2 y)
+  sphere64_q2   3D, 64^3 cells, Q2, sphere r = 0.75, u = sin(pi x) sin(pi y) sin(pi z)
+  sphere96_q3   3D, 96^3 cells, Q3, sphere r = 0.8, same u
+  balls128_q3   3D, 128^3 cells, Q3, union of 8 balls (seed 0: centres
+                U[-0.6, 0.6]^3, radii U[0.15, 0.35]), u = sin(pi x) cos(pi y) exp(z)
+
+Background box [-1, 1]^d in every case.
+"""
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Geometry:
+    kind: str                      # "balls" or "star"
+    dim: int
+    centers: np.ndarray = None     # balls: (m, dim)
+    radii: np.ndarray = None       # balls: (m,)
+    star_r0: float = 0.0
+    star_a: float = 0.0
+    star_k: int = 0
+
+    def phi(self, X):
+        """Level set (negative inside), vectorised over rows of X."""
+        X = np.atleast_2d(X)
+        if self.kind == "balls":
+            dist = np.linalg.norm(X[:, None, :] - self.centers[None], axis=2)
+            return np.min(dist - self.radii[None], axis=1)
+        th = np.arctan2(X[:, 1], X[:, 0])
+        return np.linalg.norm(X, axis=1) - (self.star_r0 + self.star_a * np.sin(self.star_k * th))
+
+
+def balls(centers, radii):
+    c = np.atleast_2d(np.asarray(centers, dtype=np.float64))
+    return Geometry("balls", c.shape[1], c, np.atleast_1d(np.asarray(radii, dtype=np.float64)))
+
+
+def star(r0, a, k):
+    return Geometry("star", 2, star_r0=float(r0), star_a=float(a), star_k=int(k))
+
+
+def eight_balls(seed=0):
+    rng = np.random.default_rng(seed)
+    centers = rng.uniform(-0.6, 0.6, (8, 3))
+    radii = rng.uniform(0.15, 0.35, 8)
+    return balls(centers, radii)
+
+
+# ---------------------------------------------------------------- solutions
+@dataclasses.dataclass
+class Solution:
+    name: str
+    u: callable
+    f: callable          # f = -Laplace(u)
+
+
+def _sinprod(d):
+    def u(X):
+        return np.prod(np.sin(math.pi * np.atleast_2d(X)[:, :d]), axis=1)
+
+    def f(X):
+        return d * math.pi ** 2 * u(X)
+    return Solution("sin(pi x_i) product", u, f)
+
+
+def _expcos():
+    def u(X):
+        X = np.atleast_2d(X)
+        return np.exp(X[:, 0]) * np.cos(2.0 * X[:, 1])
+
+    def f(X):
+        return 3.0 * u(X)
+    return Solution("exp(x) cos(2y)", u, f)
+
+
+def _sincosexp():
+    def u(X):
+        X = np.atleast_2d(X)
+        return np.sin(math.pi * X[:, 0]) * np.cos(math.pi * X[:, 1]) * np.exp(X[:, 2])
+
+    def f(X):
+        return (2.0 * math.pi ** 2 - 1.0) * u(X)
+    return Solution("sin(pi x) cos(pi y) exp(z)", u, f)
+
+
+def linear(a, c=0.0):
+    a = np.asarray(a, dtype=np.float64)
+
+    def u(X):
+        return np.atleast_2d(X) @ a + c
+
+    def f(X):
+        return np.zeros(np.atleast_2d(X).shape[0])
+    return Solution("linear", u, f)
+
+
+@dataclasses.dataclass
+class Problem:
+    name: str
+    geometry: Geometry
+    n: int
+    p: int
+    solution: Solution
+
+    @property
+    def dim(self):
+        return self.geometry.dim
+
+
+def problem(name):
+    if name == "disk32_q1":
+        return Problem(name, balls([[0.0, 0.0]], [0.7]), 32, 1, _sinprod(2))
+    if name == "star512_q2":
+        return Problem(name, star(0.6, 0.15, 5), 512, 2, _expcos())
+    if name == "sphere64_q2":
+        return Problem(name, balls([[0.0, 0.0, 0.0]], [0.75]), 64, 2, _sinprod(3))
+    if name == "sphere96_q3":
+        return Problem(name, balls([[0.0, 0.0, 0.0]], [0.8]), 96, 3, _sinprod(3))
+    if name == "balls128_q3":
+        return Problem(name, eight_balls(0), 128, 3, _sincosexp())
+    raise KeyError(name)
+
+
+PROBLEMS = ("disk32_q1", "star512_q2", "sphere64_q2", "sphere96_q3", "balls128_q3")
+
+
+def random_vector(n, seed=1, dtype=np.float64):
+    """x ~ N(0, 1), seeded (default seed 1)."""
+    return np.random.default_rng(seed).standard_normal(n).astype(dtype)

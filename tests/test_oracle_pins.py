@@ -1,0 +1,483 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's formulas: each checks a property that a
+plausible mistake (dropped term, wrong sign or index, transposed operand)
+would break -- closed forms, invariants, exact special cases, printed values.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from oracle import basis, dg, geometry, krylov, mg
+from paper_2506_12899_amd import workloads
+from tests.oracle_geom import oracle_geometry
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+DISK = geometry.Balls([[0.03, -0.02]], [0.7])
+SPHERE = geometry.Balls([[0.03, -0.02, 0.01]], [0.75])
+STAR = geometry.Star2D(0.6, 0.15, 5)
+UNION3 = oracle_geometry(workloads.eight_balls(0))
+UNION2 = geometry.Balls([[-0.2, 0.0], [0.25, 0.1], [0.0, -0.3]], [0.45, 0.4, 0.35])
+
+
+# --------------------------------------------------------------------- basis
+def test_gll_nodes_closed_form():
+    assert np.allclose(basis.gll_nodes(1), [0, 1], atol=0, rtol=0)
+    assert np.allclose(basis.gll_nodes(2), [0, 0.5, 1], atol=1e-15)
+    s5 = 1 / math.sqrt(5)
+    assert np.allclose(basis.gll_nodes(3), [0, (1 - s5) / 2, (1 + s5) / 2, 1], atol=1e-15)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_lagrange_cardinal_and_partition(p):
+    x = basis.gll_nodes(p)
+    V, D = basis.lagrange(x, x)
+    assert np.allclose(V, np.eye(p + 1), atol=1e-14)
+    t = np.linspace(-0.3, 1.3, 11)
+    V, D = basis.lagrange(x, t)
+    assert np.allclose(V.sum(1), 1, atol=1e-13)
+    assert np.allclose(D.sum(1), 0, atol=1e-12)
+    # reproduces t^p and its derivative
+    assert np.allclose(V @ x ** p, t ** p, atol=1e-13)
+    assert np.allclose(D @ x ** p, p * t ** (p - 1), atol=1e-12)
+
+
+@pytest.mark.parametrize("nq", [2, 3, 4, 6])
+def test_gauss_exactness(nq):
+    x, w = basis.gauss(nq)
+    for m in range(2 * nq):
+        assert abs(np.dot(w, x ** m) - 1.0 / (m + 1)) < 1e-15
+    m = 2 * nq
+    assert abs(np.dot(w, x ** m) - 1.0 / (m + 1)) > 1e-8
+
+
+# ------------------------------------------------------------- P1 patch test
+PATCH_CASES = [(DISK, 2, 16), (STAR, 2, 16), (UNION2, 2, 16), (SPHERE, 3, 8), (UNION3, 3, 10)]
+
+
+@pytest.mark.parametrize("geo,d,n", PATCH_CASES)
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("ext", [0, 1])
+def test_linear_patch(geo, d, n, p, ext):
+    """Linear u, f = 0, g = u: Taylor extension and SIPG are exact, so A I_h u = b."""
+    a = np.array([0.3, -0.7, 0.45][:d])
+    sol = workloads.linear(a, 0.2)
+    L = dg.Level(geo, d, n, p, ext=ext)
+    x = L.interpolate(sol.u)
+    b = L.rhs(sol.f, sol.u)
+    assert L.n_surr > 0
+    assert np.linalg.norm(L.A @ x - b) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_patch_fails_with_reversed_shift_sign():
+    """Planted mistake: E u = u - d.grad u (the printed sign) breaks consistency."""
+    sol = workloads.linear([0.3, -0.7], 0.2)
+    L = dg.Level(DISK, 2, 16, 2, build_matrix=False)
+    L.shifts = -L.shifts
+    L.assemble()
+    x = L.interpolate(sol.u)
+    L2 = dg.Level(DISK, 2, 16, 2)              # correct shifts for the data term
+    b = L2.rhs(sol.f, sol.u)
+    assert np.linalg.norm(L.A @ x - b) > 1e-3 * np.linalg.norm(b)
+
+
+def test_patch_fails_without_interior_penalty_consistency():
+    """Planted mistake: dropping the averaged-flux term breaks the patch test."""
+    sol = workloads.linear([0.3, -0.7], 0.2)
+    L = dg.Level(DISK, 2, 12, 1, build_matrix=False)
+    orig = L.interior_face_blocks
+
+    def broken(k):
+        B = orig(k)
+        old_sf = L.sigma_F
+        L.sigma_F = 0.0
+        Bz = orig(k)
+        L.sigma_F = old_sf
+        # keep only the penalty part: B - (flux part)
+        return [[B[a][b] - Bz[a][b] for b in (0, 1)] for a in (0, 1)]
+    L.interior_face_blocks = broken
+    L.assemble()
+    b = L.rhs(sol.f, sol.u)
+    x = L.interpolate(sol.u)
+    assert np.linalg.norm(L.A @ x - b) > 1e-3 * np.linalg.norm(b)
+
+
+# ------------------------------------------------- P2 unshifted = symmetric SPD
+@pytest.mark.parametrize("d,n,p", [(2, 8, 1), (2, 8, 2), (2, 8, 3), (3, 6, 1), (3, 6, 2)])
+def test_unshifted_symmetric_positive_definite(d, n, p):
+    geo = DISK if d == 2 else SPHERE
+    L = dg.Level(geo, d, n, p, zero_shift=True)
+    A = L.A.toarray()
+    assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
+    np.linalg.cholesky(0.5 * (A + A.T))
+
+
+def test_shifted_operator_is_not_symmetric():
+    L = dg.Level(DISK, 2, 8, 2)
+    A = L.A.toarray()
+    assert np.abs(A - A.T).max() > 1e-3 * np.abs(A).max()
+
+
+# ----------------------------------------------------- P3 closed-form blocks
+def _poly_1d(p):
+    """M, K, e0, e1, g0, g1 by exact polynomial integration (no quadrature)."""
+    x = basis.gll_nodes(p)
+    coefs = []
+    for a in range(p + 1):
+        y = np.zeros(p + 1)
+        y[a] = 1
+        coefs.append(np.polynomial.polynomial.polyfit(x, y, p))
+    P = np.polynomial.polynomial
+    M = np.zeros((p + 1, p + 1))
+    K = np.zeros((p + 1, p + 1))
+    for a in range(p + 1):
+        for b in range(p + 1):
+            M[a, b] = P.polyval(1, P.polyint(P.polymul(coefs[a], coefs[b])))
+            K[a, b] = P.polyval(1, P.polyint(P.polymul(P.polyder(coefs[a]), P.polyder(coefs[b]))))
+    e0 = np.array([P.polyval(0, c) for c in coefs])
+    e1 = np.array([P.polyval(1, c) for c in coefs])
+    g0 = np.array([P.polyval(0, P.polyder(c)) for c in coefs])
+    g1 = np.array([P.polyval(1, P.polyder(c)) for c in coefs])
+    return M, K, e0, e1, g0, g1
+
+
+def _kron_dir(mats):
+    """Kronecker product for x-fastest ordering: mats[0] acts on x."""
+    out = np.array([[1.0]])
+    for m in mats:
+        out = np.kron(m, out)
+    return out
+
+
+@pytest.mark.parametrize("d,p", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)])
+def test_interior_blocks_closed_form(d, p):
+    geo = DISK if d == 2 else SPHERE
+    n = 10 if d == 2 else 8
+    L = dg.Level(geo, d, n, p)
+    h, sig = L.h, L.sigma_F
+    M, K, e0, e1, g0, g1 = _poly_1d(p)
+    T = K / h - 0.5 * (np.outer(e1, g1) + np.outer(g1, e1)) / h \
+        + 0.5 * (np.outer(e0, g0) + np.outer(g0, e0)) / h + sig * (np.outer(e1, e1) + np.outer(e0, e0))
+    Cp = -0.5 * np.outer(e1, g0) / h + 0.5 * np.outer(g1, e0) / h - sig * np.outer(e1, e0)
+    Dint = sum(_kron_dir([T if c == k else h * M for c in range(d)]) for k in range(d))
+    interior = np.nonzero(np.all(L.nbr >= 0, axis=1))[0]
+    assert len(interior) > 0
+    K0 = interior[0]
+    assert np.abs(L.D[K0] - Dint).max() <= 1e-13 * np.abs(Dint).max()
+    Ad = L.A.tocsr()
+    for k in range(d):
+        Kp = L.nbr[K0, 2 * k + 1]
+        Ck = _kron_dir([Cp if c == k else h * M for c in range(d)])
+        blk = Ad[K0 * L.N:(K0 + 1) * L.N, Kp * L.N:(Kp + 1) * L.N].toarray()
+        assert np.abs(blk - Ck).max() <= 1e-13 * np.abs(Ck).max()
+        blkT = Ad[Kp * L.N:(Kp + 1) * L.N, K0 * L.N:(K0 + 1) * L.N].toarray()
+        assert np.abs(blkT - Ck.T).max() <= 1e-13 * np.abs(Ck).max()
+
+
+# ----------------------------------------------------- P4 dense direct solve
+@pytest.mark.parametrize("d,n,p", [(2, 8, 1), (2, 8, 2), (2, 8, 3), (3, 8, 1), (3, 8, 2)])
+def test_mg_gmres_matches_dense_solve(d, n, p):
+    # coarse 3D meshes with the centre rule can be strongly indefinite (the
+    # paper also reports erratic counts on coarse levels); this sphere is benign
+    geo = DISK if d == 2 else geometry.Balls([[0.0, 0.0, 0.0]], [0.8])
+    prob = workloads.problem("disk32_q1" if d == 2 else "sphere64_q2")
+    H = mg.Hierarchy(geo, d, n, p)
+    L = H.fine
+    b = L.rhs(prob.solution.f, prob.solution.u)
+    A = L.A.toarray()
+    xd = np.linalg.solve(A, b)
+    x, its, rel, conv, _ = krylov.fgmres(L.apply, H.vcycle, b, tol=1e-10, max_iter=200)
+    assert conv and rel <= 1e-10
+    assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(x - xd) <= kappa * 1e-10 * np.linalg.norm(xd)
+
+
+# ------------------------------------------------------------------ P5 rates
+def _rate(geo, d, ns, p, ext, sol):
+    errs = []
+    for n in ns:
+        L = dg.Level(geo, d, n, p, ext=ext)
+        x = spla.spsolve(L.A.tocsc(), L.rhs(sol.f, sol.u))
+        errs.append(L.l2_error(x, sol.u))
+    return -np.polyfit(np.log(ns), np.log(errs), 1)[0], errs
+
+
+@pytest.mark.parametrize("p,ext,ns", [(1, 0, (16, 32, 64, 128)), (1, 1, (16, 32, 64, 128)),
+                                      (2, 1, (16, 32, 64, 128)), (3, 1, (16, 32, 64))])
+def test_l2_rates_disk(p, ext, ns):
+    prob = workloads.problem("disk32_q1")
+    slope, errs = _rate(oracle_geometry(prob.geometry), 2, ns, p, ext, prob.solution)
+    assert slope >= p + 1 - 0.3, (slope, errs)
+
+
+def test_first_order_extension_rate_is_limited_for_p2():
+    """First-order Taylor extension: the O(|d|^2) extension error caps the rate near 2."""
+    prob = workloads.problem("disk32_q1")
+    slope, errs = _rate(oracle_geometry(prob.geometry), 2, (16, 32, 64, 128), 2, 0, prob.solution)
+    assert 1.7 <= slope <= 2.6, (slope, errs)
+
+
+def test_l2_rate_sphere_q1():
+    prob = workloads.problem("sphere64_q2")
+    slope, errs = _rate(oracle_geometry(prob.geometry), 3, (8, 12, 16, 24), 1, 0, prob.solution)
+    assert slope >= 1.7, (slope, errs)
+
+
+def _fig5_band():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "fig5_l2_band_2d.txt")) if not l.startswith("#")]
+    return [(int(r[0]), int(r[1]), int(r[2]), float(r[3]), float(r[4])) for r in rows if r]
+
+
+@pytest.mark.parametrize("ext", [0, 1])
+def test_fig5_band_p1(ext):
+    """Paper's own setup, p = 1: first-order Taylor (the printed method) falls
+    inside the printed lambda-band; the polynomial extension at or below it."""
+    disk = geometry.Balls([[0.0, 0.0]], [1.0])
+    sol = workloads.Solution("2cos sin", lambda X: 2 * np.cos(X[:, 0]) * np.sin(X[:, 1]),
+                             lambda X: 4 * np.cos(X[:, 0]) * np.sin(X[:, 1]))
+    for p, lev, cells, lo, hi in _fig5_band():
+        if p != 1:
+            continue
+        L = dg.Level(disk, 2, cells, 1, lo=-1.01, hi=1.01, ext=ext)
+        x = spla.spsolve(L.A.tocsc(), L.rhs(sol.f, sol.u))
+        e = L.l2_error(x, sol.u)
+        assert (lo if ext == 0 else 0.0) <= e <= hi, (lev, e, lo, hi)
+
+
+def test_fig5_band_high_order_polynomial_extension():
+    """p = 2, 3 with the polynomial extension: errors at or below the printed upper band."""
+    disk = geometry.Balls([[0.0, 0.0]], [1.0])
+    sol = workloads.Solution("2cos sin", lambda X: 2 * np.cos(X[:, 0]) * np.sin(X[:, 1]),
+                             lambda X: 4 * np.cos(X[:, 0]) * np.sin(X[:, 1]))
+    for p, lev, cells, lo, hi in _fig5_band():
+        if p == 1 or cells > 64:
+            continue
+        L = dg.Level(disk, 2, cells, p, lo=-1.01, hi=1.01, ext=1)
+        x = spla.spsolve(L.A.tocsc(), L.rhs(sol.f, sol.u))
+        assert L.l2_error(x, sol.u) <= hi, (p, lev)
+
+
+# ------------------------------------------------- P6 block-inverse identities
+@pytest.mark.parametrize("d,p", [(2, 1), (2, 3), (3, 2)])
+def test_block_inverse_identity(d, p):
+    geo = DISK if d == 2 else SPHERE
+    H = mg.Hierarchy(geo, d, 8, p)
+    for L, B in zip(H.levels, H.inv):
+        if L.n_act == 0:
+            continue
+        I = np.einsum('kij,kjl->kil', L.D, B)
+        assert np.abs(I - np.eye(L.N)).max() <= 1e-12 * max(1.0, np.abs(B).max() * np.abs(L.D).max() / 1e3)
+
+
+def test_single_cell_ssor_is_exact():
+    """One active cell: one colour-0 update with omega = 1 solves exactly."""
+    geo = geometry.Balls([[0.1, 0.1]], [0.25])
+    H = mg.Hierarchy(geo, 2, 4, 2, omega=1.0)
+    L = H.fine
+    assert L.n_act == 1
+    b = np.random.default_rng(3).standard_normal(L.n_dofs)
+    z = H.colour_update(len(H.levels) - 1, np.zeros_like(b), b, 0)
+    assert np.linalg.norm(L.A @ z - b) <= 1e-13 * np.linalg.norm(b)
+
+
+def test_repeated_colour_update_is_null_for_omega_one():
+    H = mg.Hierarchy(DISK, 2, 16, 2, omega=1.0)
+    l = len(H.levels) - 1
+    L = H.fine
+    b = np.random.default_rng(4).standard_normal(L.n_dofs)
+    z = np.zeros_like(b)
+    z = H.colour_update(l, z, b, 0)
+    z = H.colour_update(l, z, b, 1)
+    z1 = z.copy()
+    z = H.colour_update(l, z, b, 1)
+    assert np.linalg.norm(z - z1) <= 1e-14 * np.linalg.norm(z1)
+
+
+def test_colours_do_not_couple():
+    """Same-colour active cells never share a face (red-black validity)."""
+    for geo, d, n in [(STAR, 2, 24), (UNION3, 3, 12)]:
+        L = dg.Level(geo, d, n, 1, build_matrix=False)
+        nb = L.nbr
+        col = L.colour
+        for f in range(2 * d):
+            m = nb[:, f] >= 0
+            assert np.all(col[nb[m, f]] != col[m])
+
+
+# ----------------------------------------------------------- P7 transfers
+@pytest.mark.parametrize("d,p", [(2, 3), (3, 2)])
+def test_prolongation_reproduces_polynomials(d, p):
+    geo = DISK if d == 2 else SPHERE
+    n = 16 if d == 2 else 8
+    H = mg.Hierarchy(geo, d, n, p)
+    rng = np.random.default_rng(5)
+    for l in range(1, len(H.levels)):
+        Lc, Lf = H.levels[l - 1], H.levels[l]
+        # a random polynomial of coordinate degree p_c in every direction
+        pc = Lc.p
+        coef = rng.standard_normal((pc + 1,) * d)
+
+        def u(X):
+            out = np.zeros(X.shape[0])
+            for idx in np.ndindex(*coef.shape):
+                out += coef[idx] * np.prod([X[:, c] ** idx[c] for c in range(d)], axis=0)
+            return out
+        xf = H.P[l] @ Lc.interpolate(u)
+        ref = Lf.interpolate(u)
+        # fine cells with an active parent take the interpolant; the others get zero
+        ratio = Lf.n // Lc.n
+        par = Lc.cell_of[Lc.lin_index(Lf.cells // ratio)]
+        has = np.repeat(par >= 0, Lf.N)
+        assert np.abs(xf[has] - ref[has]).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+        assert np.all(xf[~has] == 0)
+
+
+# ------------------------------------------------------------- P8 / P9 (1D)
+class _Segment:
+    """Omega = (0, xi) seen from the single background cell [0, 1]."""
+    d = 1
+
+    def __init__(self, xi):
+        self.xi = xi
+
+    def phi(self, X):
+        return -np.ones(np.atleast_2d(X).shape[0])
+
+    def closest(self, X):
+        X = np.atleast_2d(X)
+        return np.where(X < 0.5, 0.0, self.xi)
+
+
+def _one_cell(xi, p, alpha, sigma):
+    return dg.Level(_Segment(xi), 1, 1, p, lo=0.0, hi=1.0, c_G=sigma / (p + 1) ** 2, alpha=alpha)
+
+
+def _onecell_expect():
+    out = []
+    for l in open(os.path.join(GOLDEN, "onecell_1d.txt")):
+        if l.startswith("#") or not l.strip():
+            continue
+        out.append(l.split())
+    return out
+
+
+XIS = np.linspace(0.4, 2.0, 17)
+
+
+def _max_imag(p, alpha, sigma, xi, sign=1.0):
+    pts, w = basis.volume_points(p + 1, 1)
+    Phi, _ = basis.tabulate(p, pts)
+    M = np.einsum('q,qi,qj->ij', w, Phi, Phi)
+    L = _one_cell(xi, p, alpha, sigma)
+    L.shifts = sign * L.shifts
+    right = np.nonzero(L.surr_s == 1)[0]
+    A = L.volume_block() + L.surrogate_blocks(right)[0]
+    ev = np.linalg.eigvals(np.linalg.solve(M[1:, 1:], A[1:, 1:]))
+    return np.max(np.abs(ev.imag))
+
+
+def test_onecell_negative_diagonal_and_spectra():
+    for row in _onecell_expect():
+        if row[0] == "diag":
+            p = int(row[1])
+            mind = min(np.min(np.diag(_one_cell(xi, p, 1.0, 5.0).D[0])) for xi in XIS)
+            assert (mind < 0) == (row[2] == "yes"), (p, mind)
+        else:
+            form, p, region, want = row[1], int(row[2]), row[3], row[4] == "yes"
+            alpha, sigma = (1.0, 5.0) if form == "qsym" else (-1.0, 0.0)
+            xs = {"1.0": [1.0], "gt1": XIS[XIS > 1.0 + 1e-12], "lt1": XIS[XIS < 1.0 - 1e-12]}[region]
+            im = max(_max_imag(p, alpha, sigma, xi) for xi in xs)
+            assert (im > 1e-8) == want, (form, p, region, im)
+
+
+def test_onecell_reversed_sign_mirrors_spectra():
+    """Planted mistake: with E u = u - d.grad u the penalty-free form turns complex for xi > 1."""
+    im = max(_max_imag(2, -1.0, 0.0, xi, sign=-1.0) for xi in XIS[XIS > 1.0 + 1e-12])
+    assert im > 1e-8
+
+
+# ----------------------------------------------------------- P10 geometry
+def test_shift_magnitudes_bounded():
+    for geo, d, n in [(DISK, 2, 32), (STAR, 2, 32), (UNION3, 3, 16)]:
+        for nn in (n, n // 2):
+            L = dg.Level(geo, d, nn, 1, build_matrix=False)
+            r = np.linalg.norm(L.shifts, axis=2) / L.h
+            assert r.max() <= math.sqrt(d) + 1e-12
+
+
+def test_closest_point_ball_exact():
+    rng = np.random.default_rng(7)
+    X = rng.uniform(-1, 1, (200, 3))
+    Y = SPHERE.closest(X)
+    c = SPHERE.centers[0]
+    assert np.allclose(np.linalg.norm(Y - c, axis=1), 0.75, atol=1e-15)
+    v1 = (X - c) / np.linalg.norm(X - c, axis=1, keepdims=True)
+    v2 = (Y - c) / 0.75
+    assert np.allclose(v1, v2, atol=1e-14)
+
+
+def test_closest_point_union_brute_force():
+    """The union projection is on Gamma and no sampled boundary point is closer."""
+    g = UNION3
+    rng = np.random.default_rng(8)
+    # dense boundary sample: points on each sphere not strictly inside another
+    S = []
+    for c, r in zip(g.centers, g.radii):
+        v = rng.standard_normal((20000, 3))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        P = c + r * v
+        inside = np.any(np.linalg.norm(P[:, None] - g.centers[None], axis=2) < g.radii[None] - 1e-12, axis=1)
+        S.append(P[~inside])
+    S = np.concatenate(S)
+    L = dg.Level(g, 3, 12, 1, build_matrix=False)
+    X = L.face_points.reshape(-1, 3)[::7]
+    Y = X + L.shifts.reshape(-1, 3)[::7]
+    assert np.abs(g.phi(Y)).max() <= 1e-12
+    dY = np.linalg.norm(Y - X, axis=1)
+    dS = np.min(np.linalg.norm(X[:, None] - S[None], axis=2), axis=1)
+    assert np.all(dY <= dS + 1e-12)
+
+
+def test_closest_point_star_orthogonal():
+    L = dg.Level(STAR, 2, 32, 2, build_matrix=False)
+    X = L.face_points.reshape(-1, 2)
+    Y = X + L.shifts.reshape(-1, 2)
+    th = np.arctan2(Y[:, 1], Y[:, 0])
+    assert np.allclose(np.linalg.norm(Y, axis=1), STAR.radius(th), atol=1e-14)
+    r, dr = STAR.radius(th), 0.15 * 5 * np.cos(5 * th)
+    t = np.stack([dr * np.cos(th) - r * np.sin(th), dr * np.sin(th) + r * np.cos(th)], 1)
+    assert np.abs(np.sum((X - Y) * t, 1)).max() <= 1e-12
+    # brute-force global minimum over the curve
+    tt = np.linspace(0, 2 * np.pi, 200001)
+    C = np.stack([STAR.radius(tt) * np.cos(tt), STAR.radius(tt) * np.sin(tt)], 1)
+    for x, y in zip(X[::17], Y[::17]):
+        assert np.linalg.norm(x - y) <= np.min(np.linalg.norm(C - x, axis=1)) + 1e-9
+
+
+def test_newton_closest_point_matches_exact_sphere():
+    """The Lagrangian-Newton projection for a general level set equals the exact one."""
+    c = np.array([0.03, -0.02, 0.01])
+    ls = geometry.LevelSet(lambda X: np.sum((X - c) ** 2, 1) - 0.75 ** 2,
+                           lambda X: 2 * (X - c),
+                           lambda X: np.broadcast_to(2 * np.eye(3), (X.shape[0], 3, 3)), 3)
+    rng = np.random.default_rng(9)
+    X = c + rng.uniform(-0.2, 0.2, (50, 3)) + 0.75 * np.array([1, 0, 0])
+    assert np.allclose(ls.closest(X), SPHERE.closest(X), atol=1e-13)
+
+
+def test_active_set_sizes_match_survey_table():
+    """Centre rule cell counts of the 2D workloads (cheap enough to recount)."""
+    L = dg.Level(DISK.__class__([[0, 0]], [0.7]), 2, 32, 1, build_matrix=False)
+    assert (L.n_act, L.n_surr, len(L.boundary_cells)) == (392, 88, 60)
+
+
+def test_level_shapes():
+    assert mg.level_shapes(32, 1) == [(32, 1), (16, 1), (8, 1), (4, 1)]
+    assert mg.level_shapes(96, 3) == [(96, 3), (96, 2), (96, 1), (48, 1), (24, 1), (12, 1), (6, 1), (3, 1)]
+    assert mg.level_shapes(128, 3)[-1] == (4, 1)
