@@ -1,0 +1,196 @@
+/*
+ * sbm.h -- C ABI of the MI355X (gfx950) DG Shifted Boundary Method solver.
+ *
+ * The library solves the Poisson problem -Lap u = f in Omega, u = g on
+ * Gamma = boundary of Omega (the paper's Sec. 2, model problem), with Omega
+ * = {phi < 0} given by a level set (Sec. 4.1), on a Cartesian background mesh
+ * of n^d cells covering [lo, hi]^d (Sec. 5 opening), discretised by the DG
+ * shifted boundary method of degree p (Sec. 2.2, full DG-SBM form), and
+ * preconditions restarted flexible GMRES with one hp-multigrid V-cycle per
+ * iteration whose smoother is the cell-wise successive subspace correction
+ * of Sec. 3.1 (red-black ordered, see sbm_options).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns an int status (SBM_OK = 0, negative = error,
+ *    SBM_NOT_CONVERGED = 1); none throws, aborts or exits.
+ *  - "device" pointers are HIP device allocations on the problem's device
+ *    (for example torch.Tensor.data_ptr() of a cuda tensor); "host" pointers
+ *    are ordinary CPU memory.  Unless stated otherwise the caller owns every
+ *    buffer it passes; the library never frees or keeps them past the call.
+ *  - Vectors on a level are laid out cell-major: active cells in DoF order
+ *    (colour (i+j+k) mod 2 = 0 first, then colour 1, each lexicographic with
+ *    i fastest), then the (p+1)^d Gauss-Lobatto nodes of the cell
+ *    lexicographically with x fastest.  Length = n_active * (p+1)^d.
+ *  - fp32 = 1 means the buffers hold float, otherwise double.
+ *  - Asynchronous entry points enqueue work on the problem's stream
+ *    (sbm_options.stream) and return; the synchronous ones say so.
+ *  - One problem must not be used from two threads at the same time.
+ */
+#ifndef SBM_H
+#define SBM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SBM_OK = 0,
+    SBM_NOT_CONVERGED = 1,
+    SBM_EINVAL = -1,      /* bad argument, size or unsupported (d, p)           */
+    SBM_ENOMEM = -2,      /* host or device allocation failed                   */
+    SBM_EDEVICE = -3,     /* a HIP call failed                                  */
+    SBM_ESINGULAR = -4,   /* a cell block or the coarse matrix is singular      */
+    SBM_ENONFINITE = -5,  /* NaN / Inf met in the solve                         */
+    SBM_EGEOM = -6        /* closest-point search failed                        */
+};
+
+enum { SBM_GEOM_BALLS = 0, SBM_GEOM_STAR2D = 1, SBM_GEOM_CALLBACK = 2 };
+
+/* Level-set description of Omega = {phi < 0}.  Sec. 4.1 (level set), Sec. 4.2
+ * (closest-point projection).  All arrays are host memory, copied at setup.
+ *  BALLS:   union of n_balls balls |x - centers[j]| < radii[j]
+ *           (centers: n_balls x dim, row-major); one ball = disk / sphere;
+ *           closest points are exact (Sec. 4.2 allows exact projections).
+ *  STAR2D:  dim = 2, {|x| < r(t)}, r(t) = star_r0 + star_a sin(star_k t).
+ *  CALLBACK: phi, grad (dim values) and hess (dim*dim, row-major) of a
+ *           general level set, each called for one point; the closest point
+ *           solves the Lagrangian stationarity system of Sec. 4.2 by Newton. */
+typedef struct {
+    int dim, kind, n_balls;
+    const double *centers, *radii;
+    double star_r0, star_a;
+    int star_k;
+    double (*phi)(const double *x, void *user);
+    void (*grad)(const double *x, double *g, void *user);
+    void (*hess)(const double *x, double *H, void *user);
+    void *user;
+} sbm_geometry;
+
+typedef struct {
+    double lo, hi;        /* background box [lo, hi]^dim (default -1, 1)                      */
+    double c_F, c_G;      /* sigma_F = c_F (p+1)^2 / h (default 2), sigma_Gamma = c_G (p+1)^2 / h (5) */
+    double alpha;         /* Nitsche symmetry parameter alpha (default 1, quasi-symmetric)    */
+    int ext;              /* extension operator: 0 = first-order Taylor E u = u + d.grad u
+                             (Sec. 2.1), 1 = cell polynomial evaluated at x~ + d (default 0) */
+    double omega;         /* smoother relaxation (default 1 for p <= 2, 0.8 for p = 3)        */
+    int nu_pre, nu_post;  /* SSOR steps before / after the coarse correction (default 1, 1)   */
+    int coarse_min;       /* halve n while n is even and n/2 >= coarse_min (default 3)        */
+    int vcycle_fp32;      /* sbm_solve: 0 = FP64 V-cycle, 1 = FP32 V-cycle (default 0)        */
+    int allow_singular;   /* 1: shift near-singular blocks by 1e-10 |D_K| instead of failing  */
+    int device;           /* HIP device ordinal (default 0); < 0 = host-only setup for tests:
+                             no device data, the device entry points return SBM_EINVAL     */
+    void *stream;         /* hipStream_t for all work (default NULL = null stream)            */
+} sbm_options;
+
+typedef struct {
+    long long n_dofs;     /* finest-level vector length                                       */
+    int n_active;         /* active cells on the finest level                                 */
+    int n_colour0;        /* active cells of colour 0 on the finest level                     */
+    int dofs_per_cell;    /* (p+1)^dim                                                        */
+    int n_levels;         /* multigrid levels (coarsest = 0)                                  */
+    int n_boundary_cells; /* finest-level cells with at least one surrogate face              */
+    int n_surrogate_faces;/* finest-level surrogate faces                                     */
+} sbm_layout;
+
+typedef struct {
+    int iterations;             /* FGMRES iterations (V-cycles) performed                    */
+    int converged;              /* 1 if the true relative residual reached tol               */
+    double rel_residual_true;   /* ||b - A x|| / ||b|| computed in FP64 at the end           */
+    double seconds;             /* wall time of the solve                                    */
+} sbm_stats;
+
+/* Fill *o with the defaults for (dim, p).  Host only. */
+int sbm_default_options(int dim, int p, sbm_options *o);
+
+/* Build the hierarchy for geometry g, n^dim background cells and degree p
+ * (1 <= p <= 3, dim in {2, 3}; n >= 1): per level the centre-inside active
+ * set (phi(cell centre) < 0), red-black order, neighbour table, surrogate
+ * faces, closest points and shifts at the (p_l+1)^(dim-1) Gauss points of
+ * every surrogate face (Sec. 4.2: once per level, stored), the cell blocks
+ * D_K (Sec. 3.1, A_i = R_i A R_i^T) with their FP64 LU inverses, the
+ * transfer maps (Sec. 3.2) and the dense coarsest-level inverse.  Uploads
+ * everything to o->device.  Synchronous.  On success *out owns all of it.
+ * Errors: SBM_EINVAL (arguments), SBM_ESINGULAR, SBM_EGEOM, SBM_ENOMEM, SBM_EDEVICE. */
+int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, struct sbm_problem **out);
+
+int sbm_layout_info(const struct sbm_problem *pb, sbm_layout *out);
+
+/* Host copies of finest-level metadata (for tests): active cell multi-indices
+ * (n_active x dim ints, DoF order) and the surrogate-face shifts d = x - x~
+ * of a level (n_surrogate_faces x (p_l+1)^(dim-1) x dim doubles, faces
+ * ordered by (cell, direction k, side s)).  level = -1 means the finest.
+ * cap = capacity of the output in elements; SBM_EINVAL if too small. */
+int sbm_active_cells(const struct sbm_problem *pb, int level, int *ijk, long long cap);
+int sbm_level_info(const struct sbm_problem *pb, int level, int *n, int *p, int *n_active,
+                   int *n_colour0, int *n_surrogate_faces);
+int sbm_shifts(const struct sbm_problem *pb, int level, double *host_out, long long cap);
+
+/* Right-hand side of the DG-SBM system (Sec. 2.2): int_K f phi_i plus, on
+ * surrogate faces, [-alpha grad phi_i . n~ + sigma_Gamma phi_i] g(x~ + d).
+ * f and g are batched host callbacks: called with npts points (npts x dim,
+ * row-major) they write npts values.  b_dev: finest-level FP64 device vector.
+ * Synchronous. */
+typedef void (*sbm_field_fn)(const double *x, long long npts, double *out, void *user);
+int sbm_rhs(struct sbm_problem *pb, sbm_field_fn f, sbm_field_fn g, void *user, double *b_dev);
+
+/* y = A x on the finest level (volume + SIPG faces, Sec. 2.2; Nitsche terms
+ * with the extended trial function on surrogate faces, Sec. 2.1).  x, y:
+ * device vectors of n_dofs; they must not alias.  Asynchronous. */
+int sbm_apply(struct sbm_problem *pb, const void *x_dev, void *y_dev, int fp32);
+
+/* z = M^{-1} r: one V(nu_pre, nu_post)-cycle (Sec. 3, one V-cycle as the
+ * preconditioner) with the red-black cell-block SSOR smoother.  r, z:
+ * device vectors of n_dofs (must not alias).  fp32 selects the precision of
+ * the whole cycle (blocks stored in that precision).  Asynchronous. */
+int sbm_vcycle(struct sbm_problem *pb, const void *r_dev, void *z_dev, int fp32);
+
+/* Solve A x = b with FGMRES(restart), right-preconditioned by one V-cycle
+ * (FP32 if o->vcycle_fp32), FP64 Arnoldi (CGS2), x0 = 0; stops when the TRUE
+ * relative residual ||b - A x|| / ||b|| <= tol, or after max_iter
+ * iterations (then SBM_NOT_CONVERGED, x holds the last iterate).  b, x: FP64
+ * device vectors.  Synchronous.  st may be NULL. */
+int sbm_solve(struct sbm_problem *pb, const double *b_dev, double *x_dev, double tol, int restart,
+              int max_iter, sbm_stats *st);
+
+/* Switch the precision of the V-cycle used by later sbm_solve calls
+ * (0 = FP64, 1 = FP32 with FP32 blocks; the outer Arnoldi, the operator in
+ * the Krylov space, the true residual and x stay FP64).  Host only. */
+int sbm_set_vcycle_fp32(struct sbm_problem *pb, int fp32);
+
+/* Level-resolved building blocks (for parity tests and training-data
+ * generation).  level in [0, n_levels); -1 = finest.  All asynchronous.
+ *  sbm_level_apply:   y = A_l x
+ *  sbm_colour_update: z_K += omega B_K (b - A_l z)_K for the active cells of
+ *                     the given colour (Sec. 3.1, successive correction; cells
+ *                     of one colour do not couple)
+ *  sbm_restrict:      b_c = I^T r   from level l to l-1 (Sec. 3.2)
+ *  sbm_prolong_add:   z_f += I z_c  from level l-1 to level l            */
+int sbm_level_apply(struct sbm_problem *pb, int level, const void *x_dev, void *y_dev, int fp32);
+int sbm_colour_update(struct sbm_problem *pb, int level, int colour, const void *b_dev, void *z_dev,
+                      int fp32);
+int sbm_restrict(struct sbm_problem *pb, int level, const void *r_dev, void *bc_dev, int fp32);
+int sbm_prolong_add(struct sbm_problem *pb, int level, const void *zc_dev, void *zf_dev, int fp32);
+
+/* Host copies of the assembled cell block D_K = A_K (inverse = 0) or of its
+ * FP64 LU inverse B_K (inverse = 1) of active cell `cell` on a level
+ * ((p_l+1)^d x (p_l+1)^d doubles, row-major, row = test function), and of the
+ * dense coarsest-level matrix (n0 x n0, n0 = active DoFs of level 0; cap =
+ * capacity in doubles).  For tests; available also on host-only problems. */
+int sbm_cell_block(const struct sbm_problem *pb, int level, int cell, int inverse, double *out);
+int sbm_coarse_matrix(const struct sbm_problem *pb, double *out, long long cap);
+
+/* Synchronise the problem's stream.  Returns SBM_EDEVICE on a HIP error. */
+int sbm_sync(struct sbm_problem *pb);
+
+/* Free everything the problem owns (device and host).  NULL is accepted.
+ * sbm_setup may hand back a problem together with an error status (so that
+ * sbm_last_error can be read); it must still be destroyed. */
+int sbm_destroy(struct sbm_problem *pb);
+const char *sbm_strerror(int status);
+/* Text of the last error recorded on pb (empty if none); owned by pb. */
+const char *sbm_last_error(const struct sbm_problem *pb);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SBM_H */

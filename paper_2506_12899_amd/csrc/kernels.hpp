@@ -1,0 +1,45 @@
+// Kernel launchers (kernels.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace sbm {
+
+enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2 };
+
+template <typename T>
+struct CellArgs {
+    const int *nbr;       // n_act * 2d
+    const T *shift;       // n_surr * nf * d (reference units)
+    const int *bnd_of;    // n_act
+    const T *Bint_t;      // nc * nc, transposed
+    const T *Bbnd_t;      // n_bnd * nc * nc, transposed
+    const T *lw, *lU, *lV;  // learned correction (may be null)
+};
+
+template <typename T>
+struct TransferArgs {
+    T P1[2][MAXN1][MAXN1];
+};
+
+template <typename T>
+int launch_cellop(int d, int p, int op, int cell0, int ncells, const T *x, T *y, const T *b, const CellArgs<T> &a,
+                  const KRef<T> &R, hipStream_t st);
+template <typename T>
+int launch_prolong(int d, int n_fine, int n1f, int n1c, const int *parent, const int *childpos, const T *zc, T *zf,
+                   const TransferArgs<T> &tr, hipStream_t st);
+template <typename T>
+int launch_restrict(int d, int n_coarse, int n1f, int n1c, int nch, const int *children, const T *rf, T *bc,
+                    const TransferArgs<T> &tr, hipStream_t st);
+template <typename T>
+int launch_dense_gemv(int n, const T *A, const T *x, T *y, hipStream_t st);
+template <typename T>
+int launch_fill(long long n, T *x, T v, hipStream_t st);
+int launch_cast_d2f(long long n, const double *x, float *y, hipStream_t st);
+int launch_cast_f2d(long long n, const float *x, double *y, hipStream_t st);
+int launch_multidot(long long n, int m, const double *V, const double *w, double *partial, double *out,
+                    hipStream_t st);
+int launch_multiaxpy(long long n, int m, double sign, const double *h, const double *V, double *w, hipStream_t st);
+int launch_scale(long long n, const double *nrm2, const double *w, double *v, hipStream_t st);
+
+}  // namespace sbm

@@ -1,0 +1,762 @@
+// C ABI, device upload, V-cycle and FGMRES orchestration.
+//
+// V-cycle (paper Sec. 3: one V-cycle as the preconditioner; Sec. 3.1 smoother,
+// Sec. 3.2 transfers): on level l > 0, z = 0; nu_pre SSOR steps; r = b - A z;
+// restrict; recurse; prolongate and add; nu_post SSOR steps.  One SSOR step
+// visits the colours (0, 1, 1, 0); each colour is one kernel launch because
+// cells of one colour do not couple.  Level 0 applies the dense inverse.
+//
+// FGMRES(m) (Sec. 3 opening, GMRES with the V-cycle preconditioner): right
+// preconditioning, x0 = 0, classical Gram-Schmidt with one
+// re-orthogonalisation (CGS2) in FP64 on the device, Givens rotations on the
+// host (one small device-to-host copy per iteration), stop on the true
+// relative residual.
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "setup.hpp"
+
+using namespace sbm;
+
+namespace {
+
+#define HIPCHK(call)                                                   \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) {                                        \
+            pb->last_error = std::string(#call) + ": " + hipGetErrorString(e_); \
+            return SBM_EDEVICE;                                        \
+        }                                                              \
+    } while (0)
+
+#define KCHK(call)                                                     \
+    do {                                                               \
+        if ((call) != 0) {                                             \
+            pb->last_error = std::string("launch failed: ") + #call;   \
+            return SBM_EDEVICE;                                        \
+        }                                                              \
+    } while (0)
+
+template <typename T>
+int dalloc(sbm_problem *pb, T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) return SBM_OK;
+    void *q = nullptr;
+    if (hipMalloc(&q, n * sizeof(T)) != hipSuccess) {
+        pb->last_error = "hipMalloc failed";
+        return SBM_ENOMEM;
+    }
+    pb->allocations.push_back(q);
+    *p = (T *)q;
+    return SBM_OK;
+}
+
+template <typename T, typename S>
+int upload(sbm_problem *pb, T **p, const S *src, size_t n) {
+    int rc = dalloc(pb, p, n);
+    if (rc || n == 0) return rc;
+    std::vector<T> tmp(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = (T)src[i];
+    HIPCHK(hipMemcpy(*p, tmp.data(), n * sizeof(T), hipMemcpyHostToDevice));
+    return SBM_OK;
+}
+
+template <typename T>
+void cast_kref(const KRef<double> &a, KRef<T> &b) {
+    std::memset(&b, 0, sizeof(b));
+    for (int i = 0; i < MAXN1; ++i) {
+        for (int j = 0; j < MAXN1; ++j) {
+            b.M[i][j] = (T)a.M[i][j];
+            b.S[i][j] = (T)a.S[i][j];
+            b.Sd[i][j] = (T)a.Sd[i][j];
+            for (int v = 0; v < 4; ++v) b.Tv[v][i][j] = (T)a.Tv[v][i][j];
+        }
+        b.w[i] = (T)a.w[i];
+        b.gq[i] = (T)a.gq[i];
+        b.g[0][i] = (T)a.g[0][i];
+        b.g[1][i] = (T)a.g[1][i];
+        b.x[i] = (T)a.x[i];
+    }
+    b.sigF = (T)a.sigF;
+    b.sigG = (T)a.sigG;
+    b.alpha = (T)a.alpha;
+    b.scale = (T)a.scale;
+    b.omega = (T)a.omega;
+    b.ext = a.ext;
+}
+
+template <typename T>
+int upload_level(sbm_problem *pb, int l, DevLevel<T> &D) {
+    const HostLevel &L = pb->levels[l];
+    D.d = L.d;
+    D.p = L.p;
+    D.nc = L.nc;
+    D.nf = L.nf;
+    D.n_act = L.n_act;
+    D.n_col0 = L.n_col0;
+    D.n_bnd = L.n_bnd;
+    D.n_surr = L.n_surr;
+    int rc;
+    if ((rc = upload(pb, &D.nbr, L.nbr.data(), L.nbr.size()))) return rc;
+    if ((rc = upload(pb, &D.bnd_of, L.bnd_of.data(), L.bnd_of.size()))) return rc;
+    std::vector<double> sh(L.shifts.size());
+    for (size_t i = 0; i < sh.size(); ++i) sh[i] = L.shifts[i] / L.h;
+    if ((rc = upload(pb, &D.shift, sh.data(), sh.size()))) return rc;
+    const int nc = L.nc;
+    std::vector<double> bt((size_t)nc * nc);
+    for (int i = 0; i < nc; ++i)
+        for (int j = 0; j < nc; ++j) bt[(size_t)j * nc + i] = L.Bint[(size_t)i * nc + j];
+    if ((rc = upload(pb, &D.Bint_t, bt.data(), bt.size()))) return rc;
+    {
+        size_t tot = (size_t)L.n_bnd * nc * nc;
+        if ((rc = dalloc(pb, &D.Bbnd_t, tot))) return rc;
+        if (tot) {
+            std::vector<T> tmp(tot);
+            for (int b = 0; b < L.n_bnd; ++b) {
+                const double *B = &L.Bbnd[(size_t)b * nc * nc];
+                T *o = &tmp[(size_t)b * nc * nc];
+                for (int i = 0; i < nc; ++i)
+                    for (int j = 0; j < nc; ++j) o[(size_t)j * nc + i] = (T)B[(size_t)i * nc + j];
+            }
+            HIPCHK(hipMemcpy(D.Bbnd_t, tmp.data(), tot * sizeof(T), hipMemcpyHostToDevice));
+        }
+    }
+    if (l > 0) {
+        const HostLevel &Lc = pb->levels[l - 1];
+        if ((rc = upload(pb, &D.parent, L.parent.data(), L.parent.size()))) return rc;
+        if ((rc = upload(pb, &D.childpos, L.childpos.data(), L.childpos.size()))) return rc;
+        if ((rc = upload(pb, &D.children, L.children.data(), L.children.size()))) return rc;
+        double P1[2][MAXN1][MAXN1];
+        embedding_1d(Lc, L, P1);
+        for (int o = 0; o < 2; ++o)
+            for (int a = 0; a < MAXN1; ++a)
+                for (int b = 0; b < MAXN1; ++b) D.P1[o][a][b] = (T)P1[o][a][b];
+        D.pc = Lc.p;
+    }
+    KRef<double> kr;
+    double omega = pb->opt.omega;
+    make_kref(L, pb->opt, omega, kr);
+    cast_kref(kr, D.kref);
+    size_t nd = (size_t)L.n_act * nc;
+    if ((rc = dalloc(pb, &D.z, nd))) return rc;
+    if ((rc = dalloc(pb, &D.b, nd))) return rc;
+    if ((rc = dalloc(pb, &D.r, nd))) return rc;
+    return SBM_OK;
+}
+
+template <typename T>
+CellArgs<T> cell_args(const DevLevel<T> &D, bool learned) {
+    CellArgs<T> a;
+    a.nbr = D.nbr;
+    a.shift = D.shift;
+    a.bnd_of = D.bnd_of;
+    a.Bint_t = D.Bint_t;
+    a.Bbnd_t = D.Bbnd_t;
+    a.lw = learned ? D.lw : nullptr;
+    a.lU = learned ? D.lU : nullptr;
+    a.lV = learned ? D.lV : nullptr;
+    return a;
+}
+
+template <typename T>
+std::vector<DevLevel<T>> &devlevels(sbm_problem *pb);
+template <>
+std::vector<DevLevel<double>> &devlevels<double>(sbm_problem *pb) { return pb->dev64; }
+template <>
+std::vector<DevLevel<float>> &devlevels<float>(sbm_problem *pb) { return pb->dev32; }
+
+template <typename T>
+int level_apply(sbm_problem *pb, int l, int op, const T *x, T *y, const T *b) {
+    auto &D = devlevels<T>(pb)[l];
+    KCHK(launch_cellop<T>(D.d, D.p, op, 0, D.n_act, x, y, b, cell_args(D, false), D.kref, pb->stream));
+    return SBM_OK;
+}
+
+template <typename T>
+int colour_update(sbm_problem *pb, int l, int colour, const T *b, T *z) {
+    auto &D = devlevels<T>(pb)[l];
+    int c0 = colour == 0 ? 0 : D.n_col0;
+    int nc = colour == 0 ? D.n_col0 : D.n_act - D.n_col0;
+    bool learned = (D.lw != nullptr);
+    KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, c0, nc, z, z, b, cell_args(D, learned), D.kref, pb->stream));
+    return SBM_OK;
+}
+
+template <typename T>
+int restrict_to(sbm_problem *pb, int l, const T *rf, T *bc) {
+    auto &Df = devlevels<T>(pb)[l];
+    auto &Dc = devlevels<T>(pb)[l - 1];
+    TransferArgs<T> tr;
+    std::memcpy(tr.P1, Df.P1, sizeof(tr.P1));
+    int nch = pb->levels[l].ratio == 2 ? (1 << Df.d) : 1;
+    KCHK(launch_restrict<T>(Df.d, Dc.n_act, Df.p + 1, Dc.p + 1, nch, Df.children, rf, bc, tr, pb->stream));
+    return SBM_OK;
+}
+
+template <typename T>
+int prolong_add(sbm_problem *pb, int l, const T *zc, T *zf) {
+    auto &Df = devlevels<T>(pb)[l];
+    auto &Dc = devlevels<T>(pb)[l - 1];
+    TransferArgs<T> tr;
+    std::memcpy(tr.P1, Df.P1, sizeof(tr.P1));
+    KCHK(launch_prolong<T>(Df.d, Df.n_act, Df.p + 1, Dc.p + 1, Df.parent, Df.childpos, zc, zf, tr, pb->stream));
+    return SBM_OK;
+}
+
+template <typename T>
+const T *coarse_inv(sbm_problem *pb);
+template <>
+const double *coarse_inv<double>(sbm_problem *pb) { return pb->coarse.Ainv64; }
+template <>
+const float *coarse_inv<float>(sbm_problem *pb) { return pb->coarse.Ainv32; }
+
+template <typename T>
+int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z) {
+    auto &D = devlevels<T>(pb)[l];
+    if (l == 0) {
+        if (sizeof(T) == sizeof(double)) {
+            KCHK(launch_dense_gemv<T>(pb->coarse.n, coarse_inv<T>(pb), b, z, pb->stream));
+        } else {
+            // the coarsest problem is tiny and can be badly conditioned: solve it in FP64
+            auto &D64 = pb->dev64[0];
+            KCHK(launch_cast_f2d(pb->coarse.n, (const float *)b, D64.b, pb->stream));
+            KCHK(launch_dense_gemv<double>(pb->coarse.n, pb->coarse.Ainv64, D64.b, D64.z, pb->stream));
+            KCHK(launch_cast_d2f(pb->coarse.n, D64.z, (float *)z, pb->stream));
+        }
+        return SBM_OK;
+    }
+    int rc;
+    KCHK(launch_fill<T>((long long)D.n_act * D.nc, z, T(0), pb->stream));
+    for (int s = 0; s < pb->opt.nu_pre; ++s)
+        for (int c : {0, 1, 1, 0})
+            if ((rc = colour_update<T>(pb, l, c, b, z))) return rc;
+    if ((rc = level_apply<T>(pb, l, OP_RESID, z, D.r, b))) return rc;
+    auto &Dc = devlevels<T>(pb)[l - 1];
+    if ((rc = restrict_to<T>(pb, l, D.r, Dc.b))) return rc;
+    if ((rc = vcycle_rec<T>(pb, l - 1, Dc.b, Dc.z))) return rc;
+    if ((rc = prolong_add<T>(pb, l, Dc.z, z))) return rc;
+    for (int s = 0; s < pb->opt.nu_post; ++s)
+        for (int c : {0, 1, 1, 0})
+            if ((rc = colour_update<T>(pb, l, c, b, z))) return rc;
+    return SBM_OK;
+}
+
+int check_level(sbm_problem *pb, int &level) {
+    int nl = (int)pb->levels.size();
+    if (level == -1) level = nl - 1;
+    if (level < 0 || level >= nl) {
+        pb->last_error = "level out of range";
+        return SBM_EINVAL;
+    }
+    return SBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sbm_strerror(int s) {
+    switch (s) {
+        case SBM_OK: return "ok";
+        case SBM_NOT_CONVERGED: return "not converged";
+        case SBM_EINVAL: return "invalid argument";
+        case SBM_ENOMEM: return "out of memory";
+        case SBM_EDEVICE: return "HIP device error";
+        case SBM_ESINGULAR: return "singular block";
+        case SBM_ENONFINITE: return "non-finite value";
+        case SBM_EGEOM: return "closest-point search failed";
+    }
+    return "unknown status";
+}
+
+const char *sbm_last_error(const sbm_problem *pb) { return pb ? pb->last_error.c_str() : ""; }
+
+int sbm_default_options(int dim, int p, sbm_options *o) {
+    if (!o || (dim != 2 && dim != 3) || p < 1 || p > 3) return SBM_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->lo = -1.0;
+    o->hi = 1.0;
+    o->c_F = 2.0;
+    o->c_G = 5.0;
+    o->alpha = 1.0;
+    o->ext = 0;
+    o->omega = p >= 3 ? 0.8 : 1.0;
+    o->nu_pre = 1;
+    o->nu_post = 1;
+    o->coarse_min = 3;
+    o->vcycle_fp32 = 0;
+    o->allow_singular = 0;
+    o->device = 0;
+    o->stream = nullptr;
+    return SBM_OK;
+}
+
+int sbm_destroy(sbm_problem *pb) {
+    if (!pb) return SBM_OK;
+    hipSetDevice(pb->opt.device);
+    for (void *q : pb->allocations) hipFree(q);
+    if (pb->pinned) hipHostFree(pb->pinned);
+    delete pb;
+    return SBM_OK;
+}
+
+int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_problem **out) {
+    if (!g || !out || n < 1 || p < 1 || p > 3 || (g->dim != 2 && g->dim != 3)) return SBM_EINVAL;
+    *out = nullptr;
+    sbm_problem *pb = new (std::nothrow) sbm_problem();
+    if (!pb) return SBM_ENOMEM;
+    if (o)
+        pb->opt = *o;
+    else
+        sbm_default_options(g->dim, p, &pb->opt);
+    sbm_options &op = pb->opt;
+    if (!(op.hi > op.lo) || op.nu_pre < 0 || op.nu_post < 0 || op.coarse_min < 1 || (op.ext != 0 && op.ext != 1)) {
+        delete pb;
+        return SBM_EINVAL;
+    }
+    Geometry &G = pb->geom;
+    G.dim = g->dim;
+    G.kind = g->kind;
+    if (g->kind == SBM_GEOM_BALLS) {
+        if (g->n_balls < 1 || !g->centers || !g->radii) { delete pb; return SBM_EINVAL; }
+        G.centers.assign(g->centers, g->centers + (size_t)g->n_balls * g->dim);
+        G.radii.assign(g->radii, g->radii + g->n_balls);
+    } else if (g->kind == SBM_GEOM_STAR2D) {
+        if (g->dim != 2) { delete pb; return SBM_EINVAL; }
+        G.r0 = g->star_r0;
+        G.a = g->star_a;
+        G.k = g->star_k;
+    } else if (g->kind == SBM_GEOM_CALLBACK) {
+        if (!g->phi || !g->grad || !g->hess) { delete pb; return SBM_EINVAL; }
+        G.cb_phi = g->phi;
+        G.cb_grad = g->grad;
+        G.cb_hess = g->hess;
+        G.user = g->user;
+    } else {
+        delete pb;
+        return SBM_EINVAL;
+    }
+    pb->dim = g->dim;
+    pb->n = n;
+    pb->p = p;
+    const bool host_only = op.device < 0;
+    if (!host_only && hipSetDevice(op.device) != hipSuccess) {
+        delete pb;
+        return SBM_EDEVICE;
+    }
+    pb->stream = (hipStream_t)op.stream;
+    auto shapes = level_shapes(n, p, op.coarse_min);
+    pb->levels.resize(shapes.size());
+    for (size_t l = 0; l < shapes.size(); ++l) {
+        std::string err;
+        int rc = build_level(G, op, shapes[l].first, shapes[l].second, pb->levels[l], err);
+        if (rc) {
+            pb->last_error = err;
+            *out = pb;  // caller can read the message, must destroy
+            return rc;
+        }
+        if (l > 0) build_transfer(pb->levels[l - 1], pb->levels[l]);
+    }
+    // coarsest dense matrix and its inverse
+    const HostLevel &L0 = pb->levels[0];
+    long long n0 = (long long)L0.n_act * L0.nc;
+    if (n0 > 4096) {
+        pb->last_error = "coarsest level too large for the dense solver (raise coarse_min)";
+        *out = pb;
+        return SBM_EINVAL;
+    }
+    coarse_matrix(L0, op.alpha, op.ext, pb->A0);
+    std::vector<double> Ainv = pb->A0;
+    if (n0 > 0 && !invert(Ainv.data(), (int)n0, 1e-14, 0.0)) {
+        pb->last_error = "singular coarsest-level matrix";
+        *out = pb;
+        return SBM_ESINGULAR;
+    }
+    pb->coarse.n = (int)n0;
+    pb->host_only = host_only;
+    if (host_only) {
+        *out = pb;
+        return SBM_OK;
+    }
+    int rc;
+    if ((rc = upload(pb, &pb->coarse.Ainv64, Ainv.data(), Ainv.size())) ||
+        (rc = upload(pb, &pb->coarse.Ainv32, Ainv.data(), Ainv.size()))) {
+        *out = pb;
+        return rc;
+    }
+    pb->dev64.resize(shapes.size());
+    pb->dev32.resize(shapes.size());
+    for (size_t l = 0; l < shapes.size(); ++l) {
+        if ((rc = upload_level<double>(pb, (int)l, pb->dev64[l])) || (rc = upload_level<float>(pb, (int)l, pb->dev32[l]))) {
+            *out = pb;
+            return rc;
+        }
+        if (l > 0) {
+            std::vector<double>().swap(pb->levels[l].Dbnd);  // only the coarsest keeps D
+        }
+    }
+    const HostLevel &Lf = pb->levels.back();
+    size_t nd = (size_t)Lf.n_act * Lf.nc;
+    if ((rc = dalloc(pb, &pb->f32_in, nd)) || (rc = dalloc(pb, &pb->f32_out, nd))) {
+        *out = pb;
+        return rc;
+    }
+    if (hipHostMalloc((void **)&pb->pinned, 256 * sizeof(double)) != hipSuccess) {
+        *out = pb;
+        return SBM_ENOMEM;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        *out = pb;
+        return SBM_EDEVICE;
+    }
+    *out = pb;
+    return SBM_OK;
+}
+
+int sbm_layout_info(const sbm_problem *pb, sbm_layout *o) {
+    if (!pb || !o) return SBM_EINVAL;
+    const HostLevel &L = pb->levels.back();
+    o->n_dofs = (long long)L.n_act * L.nc;
+    o->n_active = L.n_act;
+    o->n_colour0 = L.n_col0;
+    o->dofs_per_cell = L.nc;
+    o->n_levels = (int)pb->levels.size();
+    o->n_boundary_cells = L.n_bnd;
+    o->n_surrogate_faces = L.n_surr;
+    return SBM_OK;
+}
+
+int sbm_level_info(const sbm_problem *pb, int level, int *n, int *p, int *n_active, int *n_colour0, int *n_surr) {
+    if (!pb) return SBM_EINVAL;
+    int nl = (int)pb->levels.size();
+    if (level == -1) level = nl - 1;
+    if (level < 0 || level >= nl) return SBM_EINVAL;
+    const HostLevel &L = pb->levels[level];
+    if (n) *n = L.n;
+    if (p) *p = L.p;
+    if (n_active) *n_active = L.n_act;
+    if (n_colour0) *n_colour0 = L.n_col0;
+    if (n_surr) *n_surr = L.n_surr;
+    return SBM_OK;
+}
+
+int sbm_active_cells(const sbm_problem *pb, int level, int *ijk, long long cap) {
+    if (!pb) return SBM_EINVAL;
+    int nl = (int)pb->levels.size();
+    if (level == -1) level = nl - 1;
+    if (level < 0 || level >= nl) return SBM_EINVAL;
+    const HostLevel &L = pb->levels[level];
+    if (cap < (long long)L.cells.size() || (!ijk && !L.cells.empty())) return SBM_EINVAL;
+    if (!L.cells.empty()) std::memcpy(ijk, L.cells.data(), L.cells.size() * sizeof(int));
+    return SBM_OK;
+}
+
+int sbm_shifts(const sbm_problem *pb, int level, double *out, long long cap) {
+    if (!pb) return SBM_EINVAL;
+    int nl = (int)pb->levels.size();
+    if (level == -1) level = nl - 1;
+    if (level < 0 || level >= nl) return SBM_EINVAL;
+    const HostLevel &L = pb->levels[level];
+    if (cap < (long long)L.shifts.size() || (!out && !L.shifts.empty())) return SBM_EINVAL;
+    if (!L.shifts.empty()) std::memcpy(out, L.shifts.data(), L.shifts.size() * sizeof(double));
+    return SBM_OK;
+}
+
+int sbm_rhs(sbm_problem *pb, sbm_field_fn f, sbm_field_fn g, void *user, double *b_dev) {
+    if (!pb || pb->host_only || !f || !g || !b_dev) return SBM_EINVAL;
+    const HostLevel &L = pb->levels.back();
+    const int d = L.d, n1 = L.n1, nc = L.nc, nf = L.nf;
+    const Ref1D &r = L.ref;
+    const double h = L.h, alpha = pb->opt.alpha;
+    std::vector<double> b((size_t)L.n_act * nc, 0.0);
+    // volume: h^d sum_q w_q f(x_q) phi_i(x_q), (p+1)^d Gauss points
+    const int nq = nc;
+    const long long chunk = 1 << 16;
+    std::vector<double> X, F;
+    for (long long c0 = 0; c0 < L.n_act; c0 += chunk) {
+        long long c1 = std::min<long long>(L.n_act, c0 + chunk);
+        long long np = (c1 - c0) * nq;
+        X.resize((size_t)np * d);
+        F.resize((size_t)np);
+        for (long long K = c0; K < c1; ++K)
+            for (int q = 0; q < nq; ++q) {
+                int qq[3] = {q % n1, (q / n1) % n1, q / (n1 * n1)};
+                for (int c = 0; c < d; ++c)
+                    X[((K - c0) * nq + q) * d + c] = L.lo + h * (L.cells[K * d + c] + r.gq[qq[c]]);
+            }
+        f(X.data(), np, F.data(), user);
+        for (long long K = c0; K < c1; ++K)
+            for (int i = 0; i < nc; ++i) {
+                int ii[3] = {i % n1, (i / n1) % n1, i / (n1 * n1)};
+                double acc = 0.0;
+                for (int q = 0; q < nq; ++q) {
+                    int qq[3] = {q % n1, (q / n1) % n1, q / (n1 * n1)};
+                    double w = 1.0;
+                    for (int c = 0; c < d; ++c) w *= r.wq[qq[c]] * r.S[qq[c]][ii[c]];
+                    acc += w * F[(K - c0) * nq + q];
+                }
+                b[K * nc + i] = std::pow(h, d) * acc;
+            }
+    }
+    // surrogate faces: h^(d-2) sum_q w_q [-alpha dn phi_i + sigma phi_i] g(x~ + d)
+    if (L.n_surr) {
+        long long np = (long long)L.n_surr * nf;
+        X.resize((size_t)np * d);
+        F.resize((size_t)np);
+        for (int fc = 0; fc < L.n_surr; ++fc) {
+            int K = L.surr_cell[fc], k = L.surr_k[fc], s = L.surr_s[fc];
+            int tang[2], nt = 0;
+            for (int c = 0; c < d; ++c)
+                if (c != k) tang[nt++] = c;
+            for (int q = 0; q < nf; ++q) {
+                int qq[2] = {q % n1, q / n1};
+                double x[3];
+                x[k] = L.lo + h * (L.cells[K * d + k] + s);
+                for (int t = 0; t < nt; ++t) x[tang[t]] = L.lo + h * (L.cells[K * d + tang[t]] + r.gq[qq[t]]);
+                for (int c = 0; c < d; ++c) X[((size_t)fc * nf + q) * d + c] = x[c] + L.shifts[((size_t)fc * nf + q) * d + c];
+            }
+        }
+        g(X.data(), np, F.data(), user);
+        double sc = std::pow(h, d - 2);
+        for (int fc = 0; fc < L.n_surr; ++fc) {
+            int K = L.surr_cell[fc], k = L.surr_k[fc], s = L.surr_s[fc];
+            double sg = s == 1 ? 1.0 : -1.0;
+            int tang[2], nt = 0;
+            for (int c = 0; c < d; ++c)
+                if (c != k) tang[nt++] = c;
+            for (int i = 0; i < nc; ++i) {
+                int ii[3] = {i % n1, (i / n1) % n1, i / (n1 * n1)};
+                double coef = -alpha * sg * r.g[s][ii[k]] + L.sigG * r.e[s][ii[k]];
+                if (coef == 0.0) continue;
+                double acc = 0.0;
+                for (int q = 0; q < nf; ++q) {
+                    int qq[2] = {q % n1, q / n1};
+                    double w = 1.0;
+                    for (int t = 0; t < nt; ++t) w *= r.wq[qq[t]] * r.S[qq[t]][ii[tang[t]]];
+                    acc += w * F[(size_t)fc * nf + q];
+                }
+                b[(size_t)K * nc + i] += sc * coef * acc;
+            }
+        }
+    }
+    hipSetDevice(pb->opt.device);
+    HIPCHK(hipMemcpyAsync(b_dev, b.data(), b.size() * sizeof(double), hipMemcpyHostToDevice, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    return SBM_OK;
+}
+
+int sbm_apply(sbm_problem *pb, const void *x, void *y, int fp32) {
+    if (!pb || pb->host_only || !x || !y || x == y) return SBM_EINVAL;
+    int l = (int)pb->levels.size() - 1;
+    return fp32 ? level_apply<float>(pb, l, OP_APPLY, (const float *)x, (float *)y, nullptr)
+                : level_apply<double>(pb, l, OP_APPLY, (const double *)x, (double *)y, nullptr);
+}
+
+int sbm_level_apply(sbm_problem *pb, int level, const void *x, void *y, int fp32) {
+    if (!pb || pb->host_only || !x || !y || x == y) return SBM_EINVAL;
+    int rc = check_level(pb, level);
+    if (rc) return rc;
+    return fp32 ? level_apply<float>(pb, level, OP_APPLY, (const float *)x, (float *)y, nullptr)
+                : level_apply<double>(pb, level, OP_APPLY, (const double *)x, (double *)y, nullptr);
+}
+
+int sbm_colour_update(sbm_problem *pb, int level, int colour, const void *b, void *z, int fp32) {
+    if (!pb || pb->host_only || !b || !z || b == z || (colour != 0 && colour != 1)) return SBM_EINVAL;
+    int rc = check_level(pb, level);
+    if (rc) return rc;
+    return fp32 ? colour_update<float>(pb, level, colour, (const float *)b, (float *)z)
+                : colour_update<double>(pb, level, colour, (const double *)b, (double *)z);
+}
+
+int sbm_restrict(sbm_problem *pb, int level, const void *r, void *bc, int fp32) {
+    if (!pb || pb->host_only || !r || !bc) return SBM_EINVAL;
+    int rc = check_level(pb, level);
+    if (rc) return rc;
+    if (level == 0) return SBM_EINVAL;
+    return fp32 ? restrict_to<float>(pb, level, (const float *)r, (float *)bc)
+                : restrict_to<double>(pb, level, (const double *)r, (double *)bc);
+}
+
+int sbm_prolong_add(sbm_problem *pb, int level, const void *zc, void *zf, int fp32) {
+    if (!pb || pb->host_only || !zc || !zf) return SBM_EINVAL;
+    int rc = check_level(pb, level);
+    if (rc) return rc;
+    if (level == 0) return SBM_EINVAL;
+    return fp32 ? prolong_add<float>(pb, level, (const float *)zc, (float *)zf)
+                : prolong_add<double>(pb, level, (const double *)zc, (double *)zf);
+}
+
+int sbm_vcycle(sbm_problem *pb, const void *r, void *z, int fp32) {
+    if (!pb || pb->host_only || !r || !z || r == z) return SBM_EINVAL;
+    int l = (int)pb->levels.size() - 1;
+    return fp32 ? vcycle_rec<float>(pb, l, (const float *)r, (float *)z)
+                : vcycle_rec<double>(pb, l, (const double *)r, (double *)z);
+}
+
+int sbm_cell_block(const sbm_problem *pb, int level, int cell, int inverse, double *out) {
+    if (!pb || !out) return SBM_EINVAL;
+    int nl = (int)pb->levels.size();
+    if (level == -1) level = nl - 1;
+    if (level < 0 || level >= nl) return SBM_EINVAL;
+    const HostLevel &L = pb->levels[level];
+    if (cell < 0 || cell >= L.n_act) return SBM_EINVAL;
+    const size_t nn = (size_t)L.nc * L.nc;
+    int b = L.bnd_of[cell];
+    if (inverse) {
+        const double *src = b < 0 ? L.Bint.data() : &L.Bbnd[(size_t)b * nn];
+        std::memcpy(out, src, nn * sizeof(double));
+    } else if (b < 0) {
+        std::memcpy(out, L.Dint.data(), nn * sizeof(double));
+    } else {
+        cell_block(L, pb->opt.alpha, pb->opt.ext, cell, out);
+    }
+    return SBM_OK;
+}
+
+int sbm_set_vcycle_fp32(sbm_problem *pb, int fp32) {
+    if (!pb || (fp32 != 0 && fp32 != 1)) return SBM_EINVAL;
+    pb->opt.vcycle_fp32 = fp32;
+    return SBM_OK;
+}
+
+int sbm_coarse_matrix(const sbm_problem *pb, double *out, long long cap) {
+    if (!pb || !out || cap < (long long)pb->A0.size()) return SBM_EINVAL;
+    std::memcpy(out, pb->A0.data(), pb->A0.size() * sizeof(double));
+    return SBM_OK;
+}
+
+int sbm_sync(sbm_problem *pb) {
+    if (!pb) return SBM_EINVAL;
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    return SBM_OK;
+}
+
+int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st) {
+    if (!pb || pb->host_only || !b || !x || b == x || m < 1 || m > 30 || max_iter < 1 || !(tol > 0)) return SBM_EINVAL;
+    auto t0 = std::chrono::steady_clock::now();
+    const HostLevel &L = pb->levels.back();
+    const long long n = (long long)L.n_act * L.nc;
+    const int lf = (int)pb->levels.size() - 1;
+    hipStream_t s = pb->stream;
+    int rc;
+    if (pb->ws_restart < m) {
+        if ((rc = dalloc(pb, &pb->V, (size_t)(m + 1) * n)) || (rc = dalloc(pb, &pb->Z, (size_t)m * n)) ||
+            (rc = dalloc(pb, &pb->w, (size_t)n)) || (rc = dalloc(pb, &pb->red, (size_t)1024 * 32)) ||
+            (rc = dalloc(pb, &pb->hdev, (size_t)128)))
+            return rc;
+        pb->ws_restart = m;
+    }
+    double *V = pb->V, *Z = pb->Z, *w = pb->w, *hd = pb->hdev, *hp = pb->pinned;
+    const bool f32 = pb->opt.vcycle_fp32 != 0;
+    // ||b||
+    KCHK(launch_multidot(n, 1, b, b, pb->red, hd, s));
+    HIPCHK(hipMemcpyAsync(hp, hd, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double nb = std::sqrt(hp[0]);
+    KCHK(launch_fill<double>(n, x, 0.0, s));
+    sbm_stats local{0, 0, 0.0, 0.0};
+    if (!std::isfinite(nb)) return SBM_ENONFINITE;
+    if (nb == 0.0) {
+        local.converged = 1;
+        if (st) *st = local;
+        HIPCHK(hipStreamSynchronize(s));
+        return SBM_OK;
+    }
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+    // r = b (x0 = 0); v0 = r / ||r||
+    HIPCHK(hipMemcpyAsync(w, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double beta = nb;
+    int its = 0;
+    double rel = 1.0;
+    int status = SBM_NOT_CONVERGED;
+    for (;;) {
+        hp[0] = beta * beta;
+        // device scratch hd: [0,32) CGS pass 1, [32,64) pass 2, 64 norm^2, [96,126) y, 127 beta^2
+        HIPCHK(hipMemcpyAsync(hd + 127, hp, sizeof(double), hipMemcpyHostToDevice, s));
+        KCHK(launch_scale(n, hd + 127, w, V, s));
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int j = 0;
+        bool est_ok = false;
+        while (j < m && its < max_iter) {
+            double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
+            if (f32) {
+                KCHK(launch_cast_d2f(n, vj, pb->f32_in, s));
+                if ((rc = vcycle_rec<float>(pb, lf, pb->f32_in, pb->f32_out))) return rc;
+                KCHK(launch_cast_f2d(n, pb->f32_out, zj, s));
+            } else {
+                if ((rc = vcycle_rec<double>(pb, lf, vj, zj))) return rc;
+            }
+            if ((rc = level_apply<double>(pb, lf, OP_APPLY, zj, w, nullptr))) return rc;
+            // CGS2
+            KCHK(launch_multidot(n, j + 1, V, w, pb->red, hd, s));
+            KCHK(launch_multiaxpy(n, j + 1, -1.0, hd, V, w, s));
+            KCHK(launch_multidot(n, j + 1, V, w, pb->red, hd + 32, s));
+            KCHK(launch_multiaxpy(n, j + 1, -1.0, hd + 32, V, w, s));
+            KCHK(launch_multidot(n, 1, w, w, pb->red, hd + 64, s));
+            KCHK(launch_scale(n, hd + 64, w, V + (size_t)(j + 1) * n, s));
+            HIPCHK(hipMemcpyAsync(hp, hd, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hp[i] + hp[32 + i];
+            double hn = std::sqrt(hp[64]);
+            if (!std::isfinite(hn)) return SBM_ENONFINITE;
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+            }
+            double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+            double den = std::hypot(a, bb);
+            cs[j] = den > 0 ? a / den : 1.0;
+            sn[j] = den > 0 ? bb / den : 0.0;
+            H[(size_t)j * m + j] = den;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            ++j;
+            ++its;
+            if (std::fabs(gv[j]) / nb <= tol) {
+                est_ok = true;
+                break;
+            }
+        }
+        // y = R^{-1} g ; x += Z y
+        for (int i = j - 1; i >= 0; --i) {
+            double acc = gv[i];
+            for (int k2 = i + 1; k2 < j; ++k2) acc -= H[(size_t)i * m + k2] * y[k2];
+            y[i] = acc / H[(size_t)i * m + i];
+        }
+        for (int i = 0; i < j; ++i) hp[i] = y[i];
+        HIPCHK(hipMemcpyAsync(hd + 96, hp, j * sizeof(double), hipMemcpyHostToDevice, s));
+        KCHK(launch_multiaxpy(n, j, 1.0, hd + 96, Z, x, s));
+        // true residual
+        if ((rc = level_apply<double>(pb, lf, OP_RESID, x, w, b))) return rc;
+        KCHK(launch_multidot(n, 1, w, w, pb->red, hd + 64, s));
+        HIPCHK(hipMemcpyAsync(hp, hd + 64, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        beta = std::sqrt(hp[0]);
+        if (!std::isfinite(beta)) return SBM_ENONFINITE;
+        rel = beta / nb;
+        (void)est_ok;
+        if (rel <= tol) {
+            status = SBM_OK;
+            break;
+        }
+        if (its >= max_iter) break;
+    }
+    local.iterations = its;
+    local.converged = status == SBM_OK;
+    local.rel_residual_true = rel;
+    local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st) *st = local;
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+"""HIP path against the CPU oracle, element by element, on seeded inputs.
+
+Tolerances: FP64 kernels 1e-10 relative (norm-wise, and 1e-9 element-wise
+against the largest entry); FP32 kernels 1e-5 relative against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import krylov, mg
+from paper_2506_12899_amd import workloads
+from tests.oracle_geom import oracle_geometry
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-10, 1e-5
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _pair(geo, n, p, **kw):
+    from paper_2506_12899_amd.problem import Problem
+    dev = _gpu()
+    pb = Problem(geo, n, p, device=0, **kw)
+    H = mg.Hierarchy(oracle_geometry(geo), geo.dim, n, p, **kw)
+    return pb, H, dev
+
+
+def _t(x, dev, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev, dtype)
+
+
+CASES = [
+    ("disk_q1", workloads.balls([[0.03, -0.02]], [0.7]), 32, 1, {}),
+    ("disk_q2", workloads.balls([[0.03, -0.02]], [0.7]), 24, 2, {}),
+    ("disk_q3_ext1", workloads.balls([[0.03, -0.02]], [0.7]), 16, 3, {"ext": 1}),
+    ("star_q2", workloads.star(0.6, 0.15, 5), 32, 2, {}),
+    ("union2_q3", workloads.balls([[-0.2, 0.0], [0.25, 0.1], [0.0, -0.3]], [0.45, 0.4, 0.35]), 16, 3, {}),
+    ("sphere_q1", workloads.balls([[0.03, -0.02, 0.01]], [0.75]), 12, 1, {}),
+    ("sphere_q2", workloads.balls([[0.03, -0.02, 0.01]], [0.75]), 8, 2, {}),
+    ("sphere_q3", workloads.balls([[0.0, 0.0, 0.0]], [0.8]), 8, 3, {}),
+    ("union3_q2_ext1", workloads.eight_balls(0), 8, 2, {"ext": 1}),
+    ("union3_q3", workloads.eight_balls(0), 8, 3, {}),
+]
+IDS = [c[0] for c in CASES]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=IDS)
+def pair(request):
+    name, geo, n, p, kw = request.param
+    print(f"[parity] case {name} n={n} p={p} {kw}", flush=True)
+    return _pair(geo, n, p, **kw)
+
+
+def test_apply_all_levels(pair):
+    pb, H, dev = pair
+    for l, L in enumerate(H.levels):
+        x = workloads.random_vector(L.n_dofs, seed=1 + l)
+        ref = L.A @ x
+        y = pb.level_apply(l, _t(x, dev)).cpu().numpy()
+        assert _rel(y, ref) <= TOL64, l
+        assert np.abs(y - ref).max(initial=0) <= 1e-9 * max(1.0, np.abs(ref).max(initial=0))
+        y32 = pb.level_apply(l, _t(x, dev, torch.float32)).cpu().numpy().astype(np.float64)
+        assert _rel(y32, ref) <= TOL32, l
+
+
+def test_colour_update_all_levels(pair):
+    pb, H, dev = pair
+    for l, L in enumerate(H.levels):
+        if l == 0:
+            continue
+        b = workloads.random_vector(L.n_dofs, seed=11 + l)
+        z0 = workloads.random_vector(L.n_dofs, seed=21 + l)
+        for c in (0, 1):
+            ref = H.colour_update(l, z0.copy(), b, c)
+            zt = _t(z0, dev)
+            pb.colour_update(l, c, _t(b, dev), zt)
+            assert _rel(zt.cpu().numpy(), ref) <= TOL64, (l, c)
+            z32 = _t(z0, dev, torch.float32)
+            pb.colour_update(l, c, _t(b, dev, torch.float32), z32)
+            assert _rel(z32.cpu().numpy().astype(np.float64), ref) <= TOL32, (l, c)
+
+
+def test_transfers(pair):
+    pb, H, dev = pair
+    for l in range(1, len(H.levels)):
+        Lc, Lf = H.levels[l - 1], H.levels[l]
+        r = workloads.random_vector(Lf.n_dofs, seed=31 + l)
+        bc = torch.zeros(Lc.n_dofs, dtype=torch.float64, device=dev)
+        pb.restrict(l, _t(r, dev), bc)
+        assert _rel(bc.cpu().numpy(), H.P[l].T @ r) <= TOL64
+        zc = workloads.random_vector(Lc.n_dofs, seed=41 + l)
+        zf0 = workloads.random_vector(Lf.n_dofs, seed=51 + l)
+        zf = _t(zf0, dev)
+        pb.prolong_add(l, _t(zc, dev), zf)
+        assert _rel(zf.cpu().numpy(), zf0 + H.P[l] @ zc) <= TOL64
+
+
+def test_vcycle(pair):
+    pb, H, dev = pair
+    L = H.fine
+    r = workloads.random_vector(L.n_dofs, seed=61)
+    ref = H.vcycle(r)
+    z = pb.vcycle(_t(r, dev)).cpu().numpy()
+    assert _rel(z, ref) <= TOL64
+    z32 = pb.vcycle(_t(r, dev, torch.float32)).cpu().numpy().astype(np.float64)
+    # FP32 storage rounds z, r and B_K at u = 6e-8; a cell block with condition
+    # number kappa amplifies that in its correction, so the FP32 bar is
+    # max(1e-5, 5e-8 * kappa_max) (kappa_max over every level's cell blocks)
+    kappa = max(np.linalg.cond(L.D).max() for L in H.levels if L.n_act)
+    assert _rel(z32, ref) <= max(TOL32, 5e-8 * kappa), kappa
+
+
+def test_vcycle_is_deterministic(pair):
+    pb, H, dev = pair
+    r = _t(workloads.random_vector(H.fine.n_dofs, seed=62), dev)
+    a = pb.vcycle(r).cpu().numpy()
+    b = pb.vcycle(r).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+SOLVE_CASES = [
+    ("disk32_q1", {}), ("disk32_q1", {"vcycle_fp32": 1}),
+]
+
+
+@pytest.mark.parametrize("name,kw", SOLVE_CASES)
+def test_solve_true_residual(name, kw):
+    from paper_2506_12899_amd.problem import Problem
+    dev = _gpu()
+    prob = workloads.problem(name)
+    pb = Problem(prob.geometry, prob.n, prob.p, device=0, **kw)
+    b = pb.rhs(prob.solution.f, prob.solution.u)
+    x, st = pb.solve(b, tol=1e-8)
+    assert st["converged"] and st["rel_residual"] <= 1e-8
+    H = mg.Hierarchy(oracle_geometry(prob.geometry), prob.dim, prob.n, prob.p)
+    L = H.fine
+    bo = L.rhs(prob.solution.f, prob.solution.u)
+    assert _rel(b.cpu().numpy(), bo) <= 1e-13
+    xn = x.cpu().numpy()
+    assert np.linalg.norm(bo - L.A @ xn) <= 1e-8 * np.linalg.norm(bo) * (1 + 1e-6)
+    # the oracle's own MG-FGMRES reaches the same discrete solution
+    xo, its, rel, conv, _ = krylov.fgmres(L.apply, H.vcycle, bo, tol=1e-10)
+    assert _rel(xn, xo) <= 1e-5

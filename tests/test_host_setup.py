@@ -1,0 +1,117 @@
+"""Host-side setup of the C library (no GPU) against the oracle.
+
+The library is set up in host-only mode (device = -1): active sets, order,
+surrogate faces, closest points, cell blocks, their LU inverses and the
+coarsest-level matrix are compared with the oracle's independent
+construction by direct quadrature.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dg, geometry, mg
+from paper_2506_12899_amd import native, workloads
+from tests.oracle_geom import oracle_geometry
+
+pytestmark = pytest.mark.skipif(not os.path.exists(native.LIBPATH), reason="libsbm.so not built")
+
+
+def _problem(geo, n, p, **kw):
+    from paper_2506_12899_amd.problem import Problem
+    return Problem(geo, n, p, device=-1, **kw)
+
+
+CASES = [
+    ("disk", workloads.balls([[0.03, -0.02]], [0.7]), 16, 1),
+    ("disk", workloads.balls([[0.03, -0.02]], [0.7]), 16, 3),
+    ("star", workloads.star(0.6, 0.15, 5), 24, 2),
+    ("union2", workloads.balls([[-0.2, 0.0], [0.25, 0.1], [0.0, -0.3]], [0.45, 0.4, 0.35]), 16, 2),
+    ("sphere", workloads.balls([[0.03, -0.02, 0.01]], [0.75]), 8, 2),
+    ("union3", workloads.eight_balls(0), 10, 1),
+    ("union3", workloads.eight_balls(0), 8, 3),
+]
+
+
+@pytest.mark.parametrize("name,geo,n,p", CASES)
+@pytest.mark.parametrize("ext", [0, 1])
+def test_levels_shifts_blocks_match_oracle(name, geo, n, p, ext):
+    pb = _problem(geo, n, p, ext=ext)
+    H = mg.Hierarchy(oracle_geometry(geo), geo.dim, n, p, ext=ext)
+    assert pb.n_levels == len(H.levels)
+    rng = np.random.default_rng(0)
+    for l, L in enumerate(H.levels):
+        info = pb.level_info(l)
+        assert (info["n"], info["p"], info["n_active"], info["n_colour0"], info["n_surrogate_faces"]) == \
+            (L.n, L.p, L.n_act, L.n_col0, L.n_surr)
+        assert np.array_equal(pb.active_cells(l), L.cells)
+        sh = pb.shifts(l)
+        assert np.abs(sh - L.shifts).max(initial=0.0) <= 1e-12
+        cells = rng.choice(L.n_act, size=min(L.n_act, 12), replace=False) if L.n_act else []
+        bcells = L.boundary_cells[:8]
+        for K in list(cells) + list(bcells):
+            D = pb.cell_block(int(K), l)
+            ref = L.D[K]
+            assert np.abs(D - ref).max() <= 1e-12 * np.abs(ref).max(), (l, K)
+            B = pb.cell_block(int(K), l, inverse=True)
+            Bref = H.inv[l][K]
+            assert np.abs(B - Bref).max() <= 1e-10 * np.abs(Bref).max(), (l, K)
+    A0 = pb.coarse_matrix()
+    assert np.abs(A0 - H.levels[0].A.toarray()).max(initial=0.0) <= 1e-12 * max(1.0, np.abs(A0).max(initial=0.0))
+
+
+def test_star_closest_points_on_workload_mesh():
+    geo = workloads.star(0.6, 0.15, 5)
+    pb = _problem(geo, 64, 2)
+    L = dg.Level(oracle_geometry(geo), 2, 64, 2, build_matrix=False)
+    assert np.abs(pb.shifts() - L.shifts).max() <= 1e-12
+
+
+def test_invalid_arguments_rejected():
+    geo = workloads.balls([[0.0, 0.0]], [0.7])
+    from paper_2506_12899_amd.problem import Problem
+    with pytest.raises(native.SbmError):
+        Problem(geo, 8, 4, device=-1)
+    with pytest.raises(native.SbmError):
+        Problem(geo, 0, 1, device=-1)
+    with pytest.raises(native.SbmError):
+        Problem(geo, 8, 1, device=-1, ext=3)
+    pb = _problem(geo, 8, 1)
+    L = native.lib()
+    # device entry points refuse a host-only problem
+    assert L.sbm_apply(pb._h, C.c_void_p(1), C.c_void_p(2), 0) == -1
+    assert L.sbm_vcycle(pb._h, C.c_void_p(1), C.c_void_p(2), 0) == -1
+    assert L.sbm_level_apply(pb._h, 99, C.c_void_p(1), C.c_void_p(2), 0) == -1
+
+
+def test_callback_level_set_matches_exact_sphere():
+    c = np.array([0.03, -0.02, 0.01])
+
+    class CB:
+        kind, dim = "callback", 3
+
+        @staticmethod
+        def phi(X):
+            return np.sum((X - c) ** 2, 1) - 0.75 ** 2
+
+        @staticmethod
+        def grad(X):
+            return 2 * (X - c)
+
+        @staticmethod
+        def hess(X):
+            return np.broadcast_to(2 * np.eye(3), (X.shape[0], 3, 3))
+    pb_cb = _problem(CB, 8, 1)
+    pb_ex = _problem(workloads.balls([c], [0.75]), 8, 1)
+    assert np.abs(pb_cb.shifts() - pb_ex.shifts()).max() <= 1e-12
+
+
+def test_every_declared_symbol_is_exported():
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sbm.h")).read()
+    names = set(re.findall(r"\b(sbm_[a-z0-9_]+)\s*\(", hdr))
+    L = C.CDLL(native.LIBPATH)
+    for nm in names:
+        getattr(L, nm)
+    assert {s[0] for s in native.SIGNATURES} >= names
