@@ -44,7 +44,7 @@ enum {
     SBM_EGEOM = -6        /* closest-point search failed                        */
 };
 
-enum { SBM_GEOM_BALLS = 0, SBM_GEOM_STAR2D = 1, SBM_GEOM_CALLBACK = 2 };
+enum { SBM_GEOM_BALLS = 0, SBM_GEOM_STAR2D = 1, SBM_GEOM_CALLBACK = 2, SBM_GEOM_ELLIPSOID = 3 };
 
 /* Level-set description of Omega = {phi < 0}.  Sec. 4.1 (level set), Sec. 4.2
  * (closest-point projection).  All arrays are host memory, copied at setup.
@@ -54,10 +54,13 @@ enum { SBM_GEOM_BALLS = 0, SBM_GEOM_STAR2D = 1, SBM_GEOM_CALLBACK = 2 };
  *  STAR2D:  dim = 2, {|x| < r(t)}, r(t) = star_r0 + star_a sin(star_k t).
  *  CALLBACK: phi, grad (dim values) and hess (dim*dim, row-major) of a
  *           general level set, each called for one point; the closest point
- *           solves the Lagrangian stationarity system of Sec. 4.2 by Newton. */
+ *           solves the Lagrangian stationarity system of Sec. 4.2 by Newton.
+ *  ELLIPSOID: dim = 3, phi(x) = |diag(1/radii) R^T (x - centers)|^2 - 1 with
+ *           3 semi-axes in radii and R = rotation (3x3 row-major, columns =
+ *           principal axes); closest points by the same Newton iteration. */
 typedef struct {
     int dim, kind, n_balls;
-    const double *centers, *radii;
+    const double *centers, *radii, *rotation;
     double star_r0, star_a;
     int star_k;
     double (*phi)(const double *x, void *user);
@@ -71,7 +74,7 @@ typedef struct {
     double c_F, c_G;      /* sigma_F = c_F (p+1)^2 / h (default 2), sigma_Gamma = c_G (p+1)^2 / h (5) */
     double alpha;         /* Nitsche symmetry parameter alpha (default 1, quasi-symmetric)    */
     int ext;              /* extension operator: 0 = first-order Taylor E u = u + d.grad u
-                             (Sec. 2.1), 1 = cell polynomial evaluated at x~ + d (default 0) */
+                             (Sec. 2.1), 1 = cell polynomial evaluated at x~ + d (default 1) */
     double omega;         /* smoother relaxation (default 1 for p <= 2, 0.8 for p = 3)        */
     int nu_pre, nu_post;  /* SSOR steps before / after the coarse correction (default 1, 1)   */
     int coarse_min;       /* halve n while n is even and n/2 >= coarse_min (default 3)        */
@@ -178,6 +181,66 @@ int sbm_prolong_add(struct sbm_problem *pb, int level, const void *zc_dev, void 
  * capacity in doubles).  For tests; available also on host-only problems. */
 int sbm_cell_block(const struct sbm_problem *pb, int level, int cell, int inverse, double *out);
 int sbm_coarse_matrix(const struct sbm_problem *pb, double *out, long long cap);
+
+/* ---------------------------------------------------------------------------
+ * Learned boundary-cell correction of the smoother (not part of the paper;
+ * the paper finds the cell-wise smoother weak for p = 3 in 3D, Sec. 5.3, and
+ * leaves better smoothers to future work, Sec. 6).  On surrogate-boundary
+ * cells of the finest level the colour update becomes
+ *     z_K += omega * w_K * (B_K + U_K V_K^T) r_K,   w_K = 2 sigmoid(o_0),
+ * with (o_0, U_K, V_K) (U_K, V_K: (p+1)^d x 4, row-major) the output of a
+ * 3-layer tanh MLP on per-cell features.  Parameters are one flat FP32/FP64
+ * array: W1 (width x n_in, row-major), b1, W2 (width x width), b2,
+ * W3 (n_out x width), b3; n_out = 1 + 8 (p+1)^d.
+ *
+ * sbm_feature_dim:       n_in for a dimension (2d faces x (4 + 2d)).
+ * sbm_boundary_cells:    number (and, if cells != NULL, the active indices)
+ *                        of the finest level's boundary cells (host).
+ * sbm_boundary_features: n_boundary x n_in doubles (host): per face (k, s):
+ *                        surrogate mask, mean/min/max of d.n~/h, mean d/h,
+ *                        mean unit normal of Gamma at the projections.
+ * sbm_boundary_samples:  training rows of the boundary cells (device, FP64,
+ *                        n_boundary x (p+1)^d each): R = r_K, BR = B_K r_K,
+ *                        E = e_K for finest-level vectors r, e.  Async.
+ * sbm_set_learned:       BF16 inference (matrix cores, FP32 accumulation) on
+ *                        the features with device FP32 parameters of the
+ *                        given width (64), installs w_K, U_K, V_K and enables
+ *                        the correction; params = NULL disables it.  Sync.
+ * sbm_set_learned_arrays:install given w_K (n_boundary), U_K and V_K
+ *                        (n_boundary x (p+1)^d x 4) from host memory.  Sync.
+ * sbm_use_learned:       switch an installed correction on (1) or off (0).
+ *
+ * Training kernels (no problem needed; fp64 selects double buffers, else
+ * float; all device pointers, asynchronous on `stream`):
+ * sbm_mlp_forward:   H1, H2: batch x width, O: batch x n_out.
+ * sbm_mlp_loss_grad: L = mean_s |omega w (BR + U V^T R) - E|^2 / |E|^2 and
+ *                    dL/dO (batch x n_out); loss_s: batch, loss: 1 value.
+ *                    n_cell <= 64 (rank 4).
+ * sbm_mlp_backward:  grads (flat, as the parameters); dH: 2 x batch x width;
+ *                    work: sbm_mlp_work_elems(...) elements.
+ * sbm_adam:          one Adam step (t = 1-based), FP32.
+ * sbm_mlp_infer_bf16:O = MLP(X) in BF16 on the matrix cores (width 64,
+ *                    n_in <= 64); wbuf: sbm_mlp_infer_wbuf_elems(n_out) shorts. */
+int sbm_feature_dim(int dim);
+int sbm_boundary_cells(const struct sbm_problem *pb, int *n_boundary, int *cells, long long cap);
+int sbm_boundary_features(const struct sbm_problem *pb, double *host_out, long long cap);
+int sbm_boundary_samples(struct sbm_problem *pb, const double *r_dev, const double *e_dev, double *R_dev,
+                         double *BR_dev, double *E_dev);
+int sbm_set_learned(struct sbm_problem *pb, const float *params_dev, int width);
+int sbm_set_learned_arrays(struct sbm_problem *pb, const double *w, const double *U, const double *V);
+int sbm_use_learned(struct sbm_problem *pb, int on);
+int sbm_mlp_forward(int fp64, int n_in, int width, int n_out, int batch, const void *params, const void *X, void *H1,
+                    void *H2, void *O, void *stream);
+int sbm_mlp_loss_grad(int fp64, int batch, int n_cell, double omega, const void *O, const void *R, const void *BR,
+                      const void *E, void *dO, void *loss_s, void *loss, void *stream);
+long long sbm_mlp_work_elems(int n_in, int width, int n_out, int batch);
+int sbm_mlp_backward(int fp64, int n_in, int width, int n_out, int batch, const void *params, const void *X,
+                     const void *H1, const void *H2, const void *dO, void *grads, void *dH, void *work, void *stream);
+int sbm_adam(int n, float *params, const float *grads, float *m, float *v, int t, float lr, float b1, float b2,
+             float eps, void *stream);
+long long sbm_mlp_infer_wbuf_elems(int n_out);
+int sbm_mlp_infer_bf16(int n_in, int width, int n_out, int batch, const float *params, const float *X, float *O,
+                       short *wbuf, void *stream);
 
 /* Synchronise the problem's stream.  Returns SBM_EDEVICE on a HIP error. */
 int sbm_sync(struct sbm_problem *pb);

@@ -4,7 +4,7 @@ Follows the paper's Sec. 2 (weak form with the extension operator, SIPG form,
 full DG-SBM bilinear form and right-hand side) on a Cartesian background mesh.
 
 Readings of the paper used here (each is listed in the design notes):
-  * extension operator (ext = 0, the default) E u = u + d . grad u: the
+  * extension operator (ext = 0) E u = u + d . grad u: the
     printed definition carries the opposite sign, but only this sign gives the
     stated consistency E u*(x~) = u*(x~ + d) = g; the linear patch test pins
     it.  First-order Taylor limits the L2 rate to about h^2 for p >= 2, while
@@ -32,7 +32,7 @@ class Level:
     """One mesh level: active cells, faces, shifts and the DG-SBM matrix."""
 
     def __init__(self, geom, d, n, p, lo=-1.0, hi=1.0, c_F=2.0, c_G=5.0, alpha=1.0,
-                 ext=0, zero_shift=False, shifts=None, build_matrix=True):
+                 ext=1, zero_shift=False, shifts=None, build_matrix=True):
         if ext not in (0, 1):
             raise ValueError("ext must be 0 (first-order Taylor) or 1 (polynomial extrapolation)")
         self.geom, self.d, self.n, self.p = geom, d, n, p

@@ -61,9 +61,15 @@ struct Geometry {
     void (*cb_hess)(const double *, double *, void *) = nullptr;
     void *user = nullptr;
 
+    std::vector<double> rot;     // ellipsoid: 3x3 row-major, columns = principal axes
+
     double phi(const double *x) const;
     // nearest point of Gamma to x; returns false if the search failed
     bool closest(const double *x, double *y) const;
+    // smooth level sets (callback, ellipsoid): value, gradient, Hessian
+    double lphi(const double *x) const;
+    void lgrad(const double *x, double *g) const;
+    void lhess(const double *x, double *H) const;
 };
 
 // ---------------------------------------------------------------------------
@@ -99,6 +105,7 @@ struct DevLevel {
     int d = 2, p = 1, nc = 4, nf = 2, n_act = 0, n_col0 = 0, n_bnd = 0, n_surr = 0;
     int *nbr = nullptr;       // n_act * 2d
     int *bnd_of = nullptr;    // n_act
+    int *bnd_cells = nullptr; // n_bnd
     T *shift = nullptr;       // n_surr * nf * d, reference units d / h
     T *Bint_t = nullptr;      // transposed shared inverse, [j][i]
     T *Bbnd_t = nullptr;      // n_bnd * nc*nc transposed inverses
@@ -142,4 +149,9 @@ struct sbm_problem {
     std::vector<void *> allocations;
     std::string last_error;
     bool host_only = false;    // set up with device < 0: host data only (tests)
+    // learned boundary-cell correction of the finest level
+    bool learned_on = false;
+    int learned_nout = 0;
+    float *lrn_X = nullptr, *lrn_O = nullptr;
+    short *lrn_wbuf = nullptr;
 };

@@ -11,9 +11,10 @@
 //  * 2D star r(t) = r0 + a sin(k t): the squared distance is sampled at 4096
 //    equispaced t; the best sample (smallest t on ties) seeds a bracketed
 //    Newton iteration on the derivative.
-//  * callback level set: Newton on the stationarity conditions of the
-//    Lagrangian |x - x~|^2 + mu phi(x) (Sec. 4.2), started from the
-//    first-order projection x~ - phi grad phi / |grad phi|^2.
+//  * callback level set and ellipsoid (phi = |diag(1/a) R^T (x - c)|^2 - 1):
+//    Newton on the stationarity conditions of the Lagrangian
+//    |x - x~|^2 + mu phi(x) (Sec. 4.2), started from the first-order
+//    projection x~ - phi grad phi / |grad phi|^2.
 #include <cmath>
 #include <limits>
 
@@ -45,7 +46,51 @@ double Geometry::phi(const double *x) const {
         double t = std::atan2(x[1], x[0]);
         return std::sqrt(x[0] * x[0] + x[1] * x[1]) - (r0 + a * std::sin(k * t));
     }
-    return cb_phi(x, user);
+    return lphi(x);
+}
+
+// ellipsoid: phi(x) = |diag(1/a) R^T (x - c)|^2 - 1
+static void ell_local(const Geometry &g, const double *x, double *y) {
+    for (int i = 0; i < 3; ++i) {
+        double s = 0.0;
+        for (int c = 0; c < 3; ++c) s += g.rot[c * 3 + i] * (x[c] - g.centers[c]);
+        y[i] = s;
+    }
+}
+
+double Geometry::lphi(const double *x) const {
+    if (kind != SBM_GEOM_ELLIPSOID) return cb_phi(x, user);
+    double y[3], s = 0.0;
+    ell_local(*this, x, y);
+    for (int i = 0; i < 3; ++i) s += (y[i] / radii[i]) * (y[i] / radii[i]);
+    return s - 1.0;
+}
+
+void Geometry::lgrad(const double *x, double *gr) const {
+    if (kind != SBM_GEOM_ELLIPSOID) {
+        cb_grad(x, gr, user);
+        return;
+    }
+    double y[3];
+    ell_local(*this, x, y);
+    for (int c = 0; c < 3; ++c) {
+        double s = 0.0;
+        for (int i = 0; i < 3; ++i) s += rot[c * 3 + i] * 2.0 * y[i] / (radii[i] * radii[i]);
+        gr[c] = s;
+    }
+}
+
+void Geometry::lhess(const double *x, double *H) const {
+    if (kind != SBM_GEOM_ELLIPSOID) {
+        cb_hess(x, H, user);
+        return;
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int i = 0; i < 3; ++i) s += rot[a * 3 + i] * rot[b * 3 + i] * 2.0 / (radii[i] * radii[i]);
+            H[a * 3 + b] = s;
+        }
 }
 
 namespace {
@@ -237,13 +282,13 @@ bool star_closest(const Geometry &g, const double *x, double *y) {
 bool newton_closest(const Geometry &g, const double *xt, double *y) {
     const int d = g.dim;
     double x[3], gr[3], H[9];
-    double f = g.cb_phi(xt, g.user);
-    g.cb_grad(xt, gr, g.user);
+    double f = g.lphi(xt);
+    g.lgrad(xt, gr);
     double gg = 0;
     for (int c = 0; c < d; ++c) gg += gr[c] * gr[c];
     if (!(gg > 0)) return false;
     for (int c = 0; c < d; ++c) x[c] = xt[c] - f * gr[c] / gg;
-    g.cb_grad(x, gr, g.user);
+    g.lgrad(x, gr);
     gg = 0;
     double dg = 0;
     for (int c = 0; c < d; ++c) {
@@ -252,9 +297,9 @@ bool newton_closest(const Geometry &g, const double *xt, double *y) {
     }
     double mu = -2.0 * dg / gg;
     for (int it = 0; it < 100; ++it) {
-        f = g.cb_phi(x, g.user);
-        g.cb_grad(x, gr, g.user);
-        g.cb_hess(x, H, g.user);
+        f = g.lphi(x);
+        g.lgrad(x, gr);
+        g.lhess(x, H);
         double res[4], rn = 0;
         for (int c = 0; c < d; ++c) {
             res[c] = 2.0 * (x[c] - xt[c]) + mu * gr[c];
@@ -295,7 +340,7 @@ bool newton_closest(const Geometry &g, const double *xt, double *y) {
         mu += s[d];
     }
     for (int c = 0; c < d; ++c) y[c] = x[c];
-    return std::fabs(g.cb_phi(x, g.user)) < 1e-10;
+    return std::fabs(g.lphi(x)) < 1e-10;
 }
 
 }  // namespace

@@ -104,6 +104,7 @@ int upload_level(sbm_problem *pb, int l, DevLevel<T> &D) {
     int rc;
     if ((rc = upload(pb, &D.nbr, L.nbr.data(), L.nbr.size()))) return rc;
     if ((rc = upload(pb, &D.bnd_of, L.bnd_of.data(), L.bnd_of.size()))) return rc;
+    if ((rc = upload(pb, &D.bnd_cells, L.bnd_cells.data(), L.bnd_cells.size()))) return rc;
     std::vector<double> sh(L.shifts.size());
     for (size_t i = 0; i < sh.size(); ++i) sh[i] = L.shifts[i] / L.h;
     if ((rc = upload(pb, &D.shift, sh.data(), sh.size()))) return rc;
@@ -182,7 +183,7 @@ int colour_update(sbm_problem *pb, int l, int colour, const T *b, T *z) {
     auto &D = devlevels<T>(pb)[l];
     int c0 = colour == 0 ? 0 : D.n_col0;
     int nc = colour == 0 ? D.n_col0 : D.n_act - D.n_col0;
-    bool learned = (D.lw != nullptr);
+    bool learned = pb->learned_on && D.lw != nullptr && l == (int)pb->levels.size() - 1;
     KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, c0, nc, z, z, b, cell_args(D, learned), D.kref, pb->stream));
     return SBM_OK;
 }
@@ -284,7 +285,7 @@ int sbm_default_options(int dim, int p, sbm_options *o) {
     o->c_F = 2.0;
     o->c_G = 5.0;
     o->alpha = 1.0;
-    o->ext = 0;
+    o->ext = 1;
     o->omega = p >= 3 ? 0.8 : 1.0;
     o->nu_pre = 1;
     o->nu_post = 1;
@@ -331,6 +332,13 @@ int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_pro
         G.r0 = g->star_r0;
         G.a = g->star_a;
         G.k = g->star_k;
+    } else if (g->kind == SBM_GEOM_ELLIPSOID) {
+        if (g->dim != 3 || !g->centers || !g->radii || !g->rotation) { delete pb; return SBM_EINVAL; }
+        G.centers.assign(g->centers, g->centers + 3);
+        G.radii.assign(g->radii, g->radii + 3);
+        G.rot.assign(g->rotation, g->rotation + 9);
+        for (double r : G.radii)
+            if (!(r > 0)) { delete pb; return SBM_EINVAL; }
     } else if (g->kind == SBM_GEOM_CALLBACK) {
         if (!g->phi || !g->grad || !g->hess) { delete pb; return SBM_EINVAL; }
         G.cb_phi = g->phi;

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libsbm.so")
 
 SBM_OK, SBM_NOT_CONVERGED = 0, 1
-GEOM_BALLS, GEOM_STAR2D, GEOM_CALLBACK = 0, 1, 2
+GEOM_BALLS, GEOM_STAR2D, GEOM_CALLBACK, GEOM_ELLIPSOID = 0, 1, 2, 3
 
 PHI_FN = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.c_void_p)
 VEC_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
@@ -24,6 +24,7 @@ FIELD_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_longlong, C.POINTER(C.c_
 class Geometry(C.Structure):
     _fields_ = [("dim", C.c_int), ("kind", C.c_int), ("n_balls", C.c_int),
                 ("centers", C.POINTER(C.c_double)), ("radii", C.POINTER(C.c_double)),
+                ("rotation", C.POINTER(C.c_double)),
                 ("star_r0", C.c_double), ("star_a", C.c_double), ("star_k", C.c_int),
                 ("phi", PHI_FN), ("grad", VEC_FN), ("hess", VEC_FN), ("user", C.c_void_p)]
 
@@ -69,6 +70,20 @@ SIGNATURES = [
     ("sbm_cell_block", C.c_int, [_VP, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     ("sbm_coarse_matrix", C.c_int, [_VP, C.POINTER(C.c_double), C.c_longlong]),
     ("sbm_set_vcycle_fp32", C.c_int, [_VP, C.c_int]),
+    ("sbm_feature_dim", C.c_int, [C.c_int]),
+    ("sbm_boundary_cells", C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_longlong]),
+    ("sbm_boundary_features", C.c_int, [_VP, C.POINTER(C.c_double), C.c_longlong]),
+    ("sbm_boundary_samples", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    ("sbm_set_learned", C.c_int, [_VP, _VP, C.c_int]),
+    ("sbm_set_learned_arrays", C.c_int, [_VP] + [C.POINTER(C.c_double)] * 3),
+    ("sbm_use_learned", C.c_int, [_VP, C.c_int]),
+    ("sbm_mlp_forward", C.c_int, [C.c_int] * 5 + [_VP] * 6),
+    ("sbm_mlp_loss_grad", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double] + [_VP] * 8),
+    ("sbm_mlp_work_elems", C.c_longlong, [C.c_int] * 4),
+    ("sbm_mlp_backward", C.c_int, [C.c_int] * 5 + [_VP] * 9),
+    ("sbm_adam", C.c_int, [C.c_int, _VP, _VP, _VP, _VP, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, _VP]),
+    ("sbm_mlp_infer_wbuf_elems", C.c_longlong, [C.c_int]),
+    ("sbm_mlp_infer_bf16", C.c_int, [C.c_int] * 4 + [_VP] * 5),
     ("sbm_sync", C.c_int, [_VP]),
     ("sbm_destroy", C.c_int, [_VP]),
     ("sbm_strerror", C.c_char_p, [C.c_int]),

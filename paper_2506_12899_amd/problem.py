@@ -42,6 +42,15 @@ class Problem:
             g.n_balls = len(r)
             g.centers = c.ctypes.data_as(C.POINTER(C.c_double))
             g.radii = r.ctypes.data_as(C.POINTER(C.c_double))
+        elif geometry.kind == "ellipsoid":
+            c = np.ascontiguousarray(np.ravel(geometry.centers), dtype=np.float64)
+            r = np.ascontiguousarray(geometry.radii, dtype=np.float64)
+            R = np.ascontiguousarray(geometry.rotation, dtype=np.float64)
+            self._keep += [c, r, R]
+            g.kind = N.GEOM_ELLIPSOID
+            g.centers = c.ctypes.data_as(C.POINTER(C.c_double))
+            g.radii = r.ctypes.data_as(C.POINTER(C.c_double))
+            g.rotation = R.ctypes.data_as(C.POINTER(C.c_double))
         elif geometry.kind == "star":
             g.kind = N.GEOM_STAR2D
             g.star_r0, g.star_a, g.star_k = geometry.star_r0, geometry.star_a, geometry.star_k
@@ -80,7 +89,10 @@ class Problem:
 
     def __del__(self):
         if getattr(self, "_h", None) is not None:
-            N.lib().sbm_destroy(self._h)
+            try:
+                N.lib().sbm_destroy(self._h)
+            except Exception:  # interpreter shutdown: the library is already gone
+                pass
             self._h = None
 
     close = __del__

@@ -32,6 +32,7 @@ class Geometry:
     star_r0: float = 0.0
     star_a: float = 0.0
     star_k: int = 0
+    rotation: np.ndarray = None    # ellipsoid: 3x3, columns = principal axes
 
     def phi(self, X):
         """Level set (negative inside), vectorised over rows of X."""
@@ -39,6 +40,9 @@ class Geometry:
         if self.kind == "balls":
             dist = np.linalg.norm(X[:, None, :] - self.centers[None], axis=2)
             return np.min(dist - self.radii[None], axis=1)
+        if self.kind == "ellipsoid":
+            Y = (X - self.centers[0]) @ self.rotation
+            return np.sum((Y / self.radii) ** 2, axis=1) - 1.0
         th = np.arctan2(X[:, 1], X[:, 0])
         return np.linalg.norm(X, axis=1) - (self.star_r0 + self.star_a * np.sin(self.star_k * th))
 
@@ -50,6 +54,31 @@ def balls(centers, radii):
 
 def star(r0, a, k):
     return Geometry("star", 2, star_r0=float(r0), star_a=float(a), star_k=int(k))
+
+
+def ellipsoid(center, semi_axes, rotation):
+    return Geometry("ellipsoid", 3, np.atleast_2d(np.asarray(center, dtype=np.float64)),
+                    np.asarray(semi_axes, dtype=np.float64), rotation=np.asarray(rotation, dtype=np.float64))
+
+
+def random_rotation(rng):
+    """Uniform random rotation (QR of a Gaussian matrix, sign-fixed, det +1)."""
+    Q, R = np.linalg.qr(rng.standard_normal((3, 3)))
+    Q = Q * np.sign(np.diag(R))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    return Q
+
+
+def training_geometry(seed):
+    """Seeded sphere (odd seeds) or ellipsoid (even seeds) for the learned
+    correction's training data: centre U[-0.1, 0.1]^3, radius / semi-axes
+    U[0.5, 0.85], random rotation."""
+    rng = np.random.default_rng(1000 + seed)
+    c = rng.uniform(-0.1, 0.1, 3)
+    if seed % 2:
+        return balls([c], [rng.uniform(0.5, 0.85)])
+    return ellipsoid(c, rng.uniform(0.5, 0.85, 3), random_rotation(rng))
 
 
 def eight_balls(seed=0):
