@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--workload", default="star512_q2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--apply-reps", type=int, default=200)
+    ap.add_argument("--max-iter", type=int, default=300, help="FGMRES iteration cap (failure beyond it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -111,11 +112,11 @@ def main():
         pb.set_vcycle_fp32(fp32)
         st = None
         for _ in range(warmup):
-            _, st = pb.solve(b, x, tol=1e-8)
+            _, st = pb.solve(b, x, tol=1e-8, max_iter=args.max_iter)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            _, st = pb.solve(b, x, tol=1e-8)
+            _, st = pb.solve(b, x, tol=1e-8, max_iter=args.max_iter)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, st
 

@@ -215,7 +215,9 @@ int sbm_coarse_matrix(const struct sbm_problem *pb, double *out, long long cap);
  * sbm_mlp_forward:   H1, H2: batch x width, O: batch x n_out.
  * sbm_mlp_loss_grad: L = mean_s |omega w (BR + U V^T R) - E|^2 / |E|^2 and
  *                    dL/dO (batch x n_out); loss_s: batch, loss: 1 value.
- *                    n_cell <= 64 (rank 4).
+ *                    n_cell <= 64 (rank 4); a sample with E = 0 contributes
+ *                    zero; train_uv = 0 zeroes the U, V part of dL/dO (the
+ *                    relaxation weight alone is trained).
  * sbm_mlp_backward:  grads (flat, as the parameters); dH: 2 x batch x width;
  *                    work: sbm_mlp_work_elems(...) elements.
  * sbm_adam:          one Adam step (t = 1-based), FP32.
@@ -231,8 +233,8 @@ int sbm_set_learned_arrays(struct sbm_problem *pb, const double *w, const double
 int sbm_use_learned(struct sbm_problem *pb, int on);
 int sbm_mlp_forward(int fp64, int n_in, int width, int n_out, int batch, const void *params, const void *X, void *H1,
                     void *H2, void *O, void *stream);
-int sbm_mlp_loss_grad(int fp64, int batch, int n_cell, double omega, const void *O, const void *R, const void *BR,
-                      const void *E, void *dO, void *loss_s, void *loss, void *stream);
+int sbm_mlp_loss_grad(int fp64, int batch, int n_cell, int train_uv, double omega, const void *O, const void *R,
+                      const void *BR, const void *E, void *dO, void *loss_s, void *loss, void *stream);
 long long sbm_mlp_work_elems(int n_in, int width, int n_out, int batch);
 int sbm_mlp_backward(int fp64, int n_in, int width, int n_out, int batch, const void *params, const void *X,
                      const void *H1, const void *H2, const void *dO, void *grads, void *dH, void *work, void *stream);

@@ -65,9 +65,11 @@ def loss_and_dout(o, r, Br, e, omega, n_cell, rank=4):
     pred = omega * w[:, None] * P
     res = pred - e
     ne = np.sum(e * e, axis=1)
+    # a sample with e = 0 has no relative error: it contributes zero
+    inv = np.divide(1.0, ne, out=np.zeros_like(ne), where=ne > 0)
     S = o.shape[0]
-    L = np.mean(np.sum(res * res, axis=1) / ne)
-    g = 2.0 * res / ne[:, None] / S                      # dL/dpred
+    L = np.mean(np.sum(res * res, axis=1) * inv)
+    g = 2.0 * res * inv[:, None] / S                     # dL/dpred
     sig = w / 2.0
     dw = omega * np.sum(g * P, axis=1)                   # dL/dw
     do0 = dw * 2.0 * sig * (1.0 - sig)

@@ -97,268 +97,289 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
     __shared__ T ga[CPB][NFACE][NF];
     __shared__ T gb[CPB][NFACE][NF];
     __shared__ int snb[CPB][NFACE];
+    __shared__ T sB[OP == OP_SMOOTH ? NC * NC : 1];  // shared interior-cell inverse
 
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const bool slot = lane < S::CPW * NC;
     const int lc = slot ? wave * S::CPW + lane / NC : 0;
     const int i = slot ? lane % NC : 0;
-    const int lcell = blk * CPB + lc;
-    const bool live = slot && lcell < ncells;
-    const int cell = cell0 + lcell;
+    if (OP == OP_SMOOTH)
+        for (int t = threadIdx.x; t < NC * NC; t += blockDim.x) sB[t] = a.Bint_t[t];
+    // Each block owns a contiguous chunk of cell batches (one batch per block
+    // for the apply, several for the smoother so that sB is staged once per
+    // chunk); the remap gives every XCD a contiguous range of cells.
+    const int nbatch = (ncells + CPB - 1) / CPB;
+    const int chunk = OP == OP_SMOOTH ? (nbatch + gridDim.x - 1) / gridDim.x : 1;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int bb0 = blk * chunk;
+    const int bb1 = OP == OP_SMOOTH ? min(nbatch, bb0 + chunk) : bb0 + 1;
+#pragma unroll 1
+    for (int bb = bb0; bb < bb1; ++bb) {
+        const int lcell = bb * CPB + lc;
+        const bool live = slot && lcell < ncells;
+        const int cell = cell0 + lcell;
+        __syncthreads();  // the previous batch is done with the LDS buffers
 
-    if (live) {
-        su[lc][i] = xin[(size_t)cell * NC + i];
-        if (i < NFACE) snb[lc][i] = a.nbr[(size_t)cell * NFACE + i];
-    }
-    __syncthreads();
-
-    // ---------------- volume + unshifted self terms (sum factorisation)
-    T y = 0;
-    int c0 = i % N1, c1 = (i / N1) % N1, c2 = D == 3 ? i / (N1 * N1) : 0;
-    int vx = 0, vy = 0, vz = 0;
-    if (live) {
-        vx = (snb[lc][0] < 0) + 2 * (snb[lc][1] < 0);
-        vy = (snb[lc][2] < 0) + 2 * (snb[lc][3] < 0);
-        if (D == 3) vz = (snb[lc][4] < 0) + 2 * (snb[lc][5] < 0);
-        T am = 0, bt = 0;
-        int base = i - c0;
-#pragma unroll
-        for (int m = 0; m < N1; ++m) {
-            T u = su[lc][base + m];
-            am += R.M[c0][m] * u;
-            bt += R.Tv[vx][c0][m] * u;
-        }
-        sa[lc][i] = am;
-        sb[lc][i] = bt;
-    }
-    __syncthreads();
-    if (D == 2) {
         if (live) {
-#pragma unroll
-            for (int m = 0; m < N1; ++m) y += R.M[c1][m] * sb[lc][c0 + N1 * m] + R.Tv[vy][c1][m] * sa[lc][c0 + N1 * m];
-        }
-    } else {
-        T aM = 0, aT = 0, bM = 0;
-        if (live) {
-            int base = i - N1 * c1;
-#pragma unroll
-            for (int m = 0; m < N1; ++m) {
-                T av = sa[lc][base + N1 * m], bv = sb[lc][base + N1 * m];
-                aM += R.M[c1][m] * av;
-                aT += R.Tv[vy][c1][m] * av;
-                bM += R.M[c1][m] * bv;
-            }
+            su[lc][i] = xin[(size_t)cell * NC + i];
+            if (i < NFACE) snb[lc][i] = a.nbr[(size_t)cell * NFACE + i];
         }
         __syncthreads();
-        if (live) {
-            sa[lc][i] = aM;
-            sb[lc][i] = aT + bM;
-        }
-        __syncthreads();
-        if (live) {
-            int base = i - N1 * N1 * c2;
-#pragma unroll
-            for (int m = 0; m < N1; ++m)
-                y += R.M[c2][m] * sb[lc][base + N1 * N1 * m] + R.Tv[vz][c2][m] * sa[lc][base + N1 * N1 * m];
-        }
-    }
 
-    // ---------------- interior-face couplings: neighbour trace and normal derivative
-    if (live) {
-        for (int it = i; it < NFACE * NF; it += NC) {
-            int f = it / NF, j = it % NF, k = f >> 1, s = f & 1;
-            int nb = snb[lc][f];
-            T va = 0, vb = 0;
-            if (nb >= 0) {
-                const T *un = xin + (size_t)nb * NC;
-                const int layer = s == 1 ? 0 : P;
-                const T *gN = R.g[s == 1 ? 0 : 1];
-                T t = un[compose<D, P>(k, layer, j)];
-                T dn = 0;
-#pragma unroll
-                for (int m = 0; m < N1; ++m) dn += gN[m] * un[compose<D, P>(k, m, j)];
-                T sg = s == 1 ? T(1) : T(-1);
-                va = T(-0.5) * sg * dn - R.sigF * t;
-                vb = T(0.5) * t;
-            }
-            fa[lc][f][j] = va;
-            fb[lc][f][j] = vb;
-        }
-    }
-    __syncthreads();
-    // tangential mass along the first tangential direction
-    if (live) {
-        for (int it = i; it < NFACE * NF; it += NC) {
-            int f = it / NF, j = it % NF;
-            int j1 = j % N1, rest = j - j1;
-            T va = 0, vb = 0;
+        // ---------------- volume + unshifted self terms (sum factorisation)
+        T y = 0;
+        int c0 = i % N1, c1 = (i / N1) % N1, c2 = D == 3 ? i / (N1 * N1) : 0;
+        int vx = 0, vy = 0, vz = 0;
+        if (live) {
+            vx = (snb[lc][0] < 0) + 2 * (snb[lc][1] < 0);
+            vy = (snb[lc][2] < 0) + 2 * (snb[lc][3] < 0);
+            if (D == 3) vz = (snb[lc][4] < 0) + 2 * (snb[lc][5] < 0);
+            T am = 0, bt = 0;
+            int base = i - c0;
 #pragma unroll
             for (int m = 0; m < N1; ++m) {
-                va += R.M[j1][m] * fa[lc][f][rest + m];
-                vb += R.M[j1][m] * fb[lc][f][rest + m];
+                T u = su[lc][base + m];
+                am += R.M[c0][m] * u;
+                bt += R.Tv[vx][c0][m] * u;
             }
-            ga[lc][f][j] = va;
-            gb[lc][f][j] = vb;
+            sa[lc][i] = am;
+            sb[lc][i] = bt;
         }
-    }
-    __syncthreads();
-    if (D == 3) {
-        if (live) {
-            for (int it = i; it < NFACE * NF; it += NC) {
-                int f = it / NF, j = it % NF;
-                int j1 = j % N1, j2 = j / N1;
-                T va = 0, vb = 0;
+        __syncthreads();
+        if (D == 2) {
+            if (live) {
+#pragma unroll
+                for (int m = 0; m < N1; ++m) y += R.M[c1][m] * sb[lc][c0 + N1 * m] + R.Tv[vy][c1][m] * sa[lc][c0 + N1 * m];
+            }
+        } else {
+            T aM = 0, aT = 0, bM = 0;
+            if (live) {
+                int base = i - N1 * c1;
 #pragma unroll
                 for (int m = 0; m < N1; ++m) {
-                    va += R.M[j2][m] * ga[lc][f][j1 + N1 * m];
-                    vb += R.M[j2][m] * gb[lc][f][j1 + N1 * m];
+                    T av = sa[lc][base + N1 * m], bv = sb[lc][base + N1 * m];
+                    aM += R.M[c1][m] * av;
+                    aT += R.Tv[vy][c1][m] * av;
+                    bM += R.M[c1][m] * bv;
+                }
+            }
+            __syncthreads();
+            if (live) {
+                sa[lc][i] = aM;
+                sb[lc][i] = aT + bM;
+            }
+            __syncthreads();
+            if (live) {
+                int base = i - N1 * N1 * c2;
+#pragma unroll
+                for (int m = 0; m < N1; ++m)
+                    y += R.M[c2][m] * sb[lc][base + N1 * N1 * m] + R.Tv[vz][c2][m] * sa[lc][base + N1 * N1 * m];
+            }
+        }
+
+        // ---------------- interior-face couplings: neighbour trace and normal derivative
+        if (live) {
+            for (int it = i; it < NFACE * NF; it += NC) {
+                int f = it / NF, j = it % NF, k = f >> 1, s = f & 1;
+                int nb = snb[lc][f];
+                T va = 0, vb = 0;
+                if (nb >= 0) {
+                    const T *un = xin + (size_t)nb * NC;
+                    const int layer = s == 1 ? 0 : P;
+                    const T *gN = R.g[s == 1 ? 0 : 1];
+                    T t = un[compose<D, P>(k, layer, j)];
+                    T dn = 0;
+#pragma unroll
+                    for (int m = 0; m < N1; ++m) dn += gN[m] * un[compose<D, P>(k, m, j)];
+                    T sg = s == 1 ? T(1) : T(-1);
+                    va = T(-0.5) * sg * dn - R.sigF * t;
+                    vb = T(0.5) * t;
                 }
                 fa[lc][f][j] = va;
                 fb[lc][f][j] = vb;
             }
         }
         __syncthreads();
-    }
-    if (live) {
-#pragma unroll
-        for (int f = 0; f < NFACE; ++f) {
-            if (snb[lc][f] < 0) continue;
-            int k = f >> 1, s = f & 1, m, j;
-            decompose<D, P>(i, k, m, j);
-            T ev = (m == (s ? P : 0)) ? T(1) : T(0);
-            T sg = s == 1 ? T(1) : T(-1);
-            T F1 = D == 3 ? fa[lc][f][j] : ga[lc][f][j];
-            T F2 = D == 3 ? fb[lc][f][j] : gb[lc][f][j];
-            y += ev * F1 + sg * R.g[s][m] * F2;
-        }
-    }
-    __syncthreads();
-
-    // ---------------- shift part of the Nitsche terms on surrogate faces
-    bool bnd = false;
-    if (live) {
-#pragma unroll
-        for (int f = 0; f < NFACE; ++f) bnd |= snb[lc][f] < 0;
-    }
-    if (live && bnd) {
-        for (int it = i; it < NFACE * NF; it += NC) {
-            int f = it / NF, q = it % NF, k = f >> 1, s = f & 1;
-            int nb = snb[lc][f];
-            T zeta = 0;
-            if (nb < 0) {
-                int rec = -nb - 1;
-                const T *dq = a.shift + ((size_t)rec * NF + q) * D;
-                int q1 = q % N1, q2 = D == 3 ? q / N1 : 0;
-                T wq = R.w[q1] * (D == 3 ? R.w[q2] : T(1));
-                const int layer = s ? P : 0;
-                T E = 0;
-                if (R.ext == 0) {
-                    // gradient of u at the face Gauss point
-                    T dk = 0, dt1 = 0, dt2 = 0;
-#pragma unroll
-                    for (int j = 0; j < NF; ++j) {
-                        int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
-                        T s1 = R.S[q1][j1], s2 = D == 3 ? R.S[q2][j2] : T(1);
-                        T d1 = R.Sd[q1][j1], d2 = D == 3 ? R.Sd[q2][j2] : T(0);
-                        T nd = 0;
-#pragma unroll
-                        for (int m = 0; m < N1; ++m) nd += R.g[s][m] * su[lc][compose<D, P>(k, m, j)];
-                        T ul = su[lc][compose<D, P>(k, layer, j)];
-                        dk += s1 * s2 * nd;
-                        dt1 += d1 * s2 * ul;
-                        if (D == 3) dt2 += s1 * d2 * ul;
-                    }
-                    int t1 = k == 0 ? 1 : 0;
-                    int t2 = k == 2 ? 1 : 2;
-                    E = dq[k] * dk + dq[t1] * dt1;
-                    if (D == 3) E += dq[t2] * dt2;
-                } else {
-                    // cell polynomial at the shifted point minus its value at the face point
-                    T xi[3], lv[3][N1];
-                    int t1 = k == 0 ? 1 : 0;
-                    int t2 = k == 2 ? 1 : 2;
-                    xi[k] = T(s);
-                    xi[t1] = R.gq[q1];
-                    if (D == 3) xi[t2] = R.gq[q2];
-#pragma unroll
-                    for (int c = 0; c < D; ++c) lagrange_dev<T>(R.x, N1, xi[c] + dq[c], lv[c]);
-                    T acc = 0, face = 0;
-#pragma unroll
-                    for (int jj = 0; jj < NC; ++jj) {
-                        int a0 = jj % N1, a1 = (jj / N1) % N1, a2 = D == 3 ? jj / (N1 * N1) : 0;
-                        T pv = lv[0][a0] * lv[1][a1];
-                        if (D == 3) pv *= lv[2][a2];
-                        acc += pv * su[lc][jj];
-                    }
-#pragma unroll
-                    for (int j = 0; j < NF; ++j) {
-                        int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
-                        T sv = R.S[q1][j1] * (D == 3 ? R.S[q2][j2] : T(1));
-                        face += sv * su[lc][compose<D, P>(k, layer, j)];
-                    }
-                    E = acc - face;
-                }
-                zeta = wq * E;
-            }
-            fa[lc][f][q] = zeta;
-        }
-    }
-    __syncthreads();
-    if (live && bnd) {
-#pragma unroll
-        for (int f = 0; f < NFACE; ++f) {
-            if (snb[lc][f] >= 0) continue;
-            int k = f >> 1, s = f & 1, m, j;
-            decompose<D, P>(i, k, m, j);
-            T sg = s == 1 ? T(1) : T(-1);
-            T ev = (m == (s ? P : 0)) ? T(1) : T(0);
-            T coef = -R.alpha * sg * R.g[s][m] + R.sigG * ev;
-            int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
-            T acc = 0;
-#pragma unroll
-            for (int q = 0; q < NF; ++q) {
-                int q1 = q % N1, q2 = D == 3 ? q / N1 : 0;
-                T sv = R.S[q1][j1] * (D == 3 ? R.S[q2][j2] : T(1));
-                acc += fa[lc][f][q] * sv;
-            }
-            y += coef * acc;
-        }
-    }
-
-    // ---------------- output
-    y *= R.scale;
-    if (OP == OP_APPLY) {
-        if (live) out[(size_t)cell * NC + i] = y;
-    } else if (OP == OP_RESID) {
-        if (live) out[(size_t)cell * NC + i] = b[(size_t)cell * NC + i] - y;
-    } else {
-        __syncthreads();
-        if (live) sa[lc][i] = b[(size_t)cell * NC + i] - y;
-        __syncthreads();
+        // tangential mass along the first tangential direction
         if (live) {
-            int bi = a.bnd_of[cell];
-            const T *Bt = bi < 0 ? a.Bint_t : a.Bbnd_t + (size_t)bi * NC * NC;
-            T corr = 0;
-#pragma unroll 8
-            for (int j = 0; j < NC; ++j) corr += Bt[(size_t)j * NC + i] * sa[lc][j];
-            if (a.lw != nullptr && bi >= 0) {
-                const T *U = a.lU + (size_t)bi * NC * 4;
-                const T *V = a.lV + (size_t)bi * NC * 4;
-                T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-                for (int j = 0; j < NC; ++j) {
-                    T r = sa[lc][j];
-                    v0 += V[j * 4 + 0] * r;
-                    v1 += V[j * 4 + 1] * r;
-                    v2 += V[j * 4 + 2] * r;
-                    v3 += V[j * 4 + 3] * r;
+            for (int it = i; it < NFACE * NF; it += NC) {
+                int f = it / NF, j = it % NF;
+                int j1 = j % N1, rest = j - j1;
+                T va = 0, vb = 0;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) {
+                    va += R.M[j1][m] * fa[lc][f][rest + m];
+                    vb += R.M[j1][m] * fb[lc][f][rest + m];
                 }
-                corr += U[i * 4 + 0] * v0 + U[i * 4 + 1] * v1 + U[i * 4 + 2] * v2 + U[i * 4 + 3] * v3;
-                corr *= a.lw[bi];
+                ga[lc][f][j] = va;
+                gb[lc][f][j] = vb;
             }
-            out[(size_t)cell * NC + i] = su[lc][i] + R.omega * corr;
         }
-    }
+        __syncthreads();
+        if (D == 3) {
+            if (live) {
+                for (int it = i; it < NFACE * NF; it += NC) {
+                    int f = it / NF, j = it % NF;
+                    int j1 = j % N1, j2 = j / N1;
+                    T va = 0, vb = 0;
+#pragma unroll
+                    for (int m = 0; m < N1; ++m) {
+                        va += R.M[j2][m] * ga[lc][f][j1 + N1 * m];
+                        vb += R.M[j2][m] * gb[lc][f][j1 + N1 * m];
+                    }
+                    fa[lc][f][j] = va;
+                    fb[lc][f][j] = vb;
+                }
+            }
+            __syncthreads();
+        }
+        if (live) {
+#pragma unroll
+            for (int f = 0; f < NFACE; ++f) {
+                if (snb[lc][f] < 0) continue;
+                int k = f >> 1, s = f & 1, m, j;
+                decompose<D, P>(i, k, m, j);
+                T ev = (m == (s ? P : 0)) ? T(1) : T(0);
+                T sg = s == 1 ? T(1) : T(-1);
+                T F1 = D == 3 ? fa[lc][f][j] : ga[lc][f][j];
+                T F2 = D == 3 ? fb[lc][f][j] : gb[lc][f][j];
+                y += ev * F1 + sg * R.g[s][m] * F2;
+            }
+        }
+        __syncthreads();
+
+        // ---------------- shift part of the Nitsche terms on surrogate faces
+        bool bnd = false;
+        if (live) {
+#pragma unroll
+            for (int f = 0; f < NFACE; ++f) bnd |= snb[lc][f] < 0;
+        }
+        if (live && bnd) {
+            for (int it = i; it < NFACE * NF; it += NC) {
+                int f = it / NF, q = it % NF, k = f >> 1, s = f & 1;
+                int nb = snb[lc][f];
+                T zeta = 0;
+                if (nb < 0) {
+                    int rec = -nb - 1;
+                    const T *dq = a.shift + ((size_t)rec * NF + q) * D;
+                    int q1 = q % N1, q2 = D == 3 ? q / N1 : 0;
+                    T wq = R.w[q1] * (D == 3 ? R.w[q2] : T(1));
+                    const int layer = s ? P : 0;
+                    T E = 0;
+                    // boundary cells only: loops stay rolled to keep register pressure
+                    // of the whole kernel low
+                    if (R.ext == 0) {
+                        // gradient of u at the face Gauss point
+                        T dk = 0, dt1 = 0, dt2 = 0;
+#pragma unroll 1
+                        for (int j = 0; j < NF; ++j) {
+                            int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
+                            T s1 = R.S[q1][j1], s2 = D == 3 ? R.S[q2][j2] : T(1);
+                            T d1 = R.Sd[q1][j1], d2 = D == 3 ? R.Sd[q2][j2] : T(0);
+                            T nd = 0;
+#pragma unroll
+                            for (int m = 0; m < N1; ++m) nd += R.g[s][m] * su[lc][compose<D, P>(k, m, j)];
+                            T ul = su[lc][compose<D, P>(k, layer, j)];
+                            dk += s1 * s2 * nd;
+                            dt1 += d1 * s2 * ul;
+                            if (D == 3) dt2 += s1 * d2 * ul;
+                        }
+                        int t1 = k == 0 ? 1 : 0;
+                        int t2 = k == 2 ? 1 : 2;
+                        E = dq[k] * dk + dq[t1] * dt1;
+                        if (D == 3) E += dq[t2] * dt2;
+                    } else {
+                        // cell polynomial at the shifted point minus its value at the face point
+                        T lv[3][N1];
+                        const int t1 = k == 0 ? 1 : 0;
+#pragma unroll
+                        for (int c = 0; c < D; ++c) {
+                            T xc = c == k ? T(s) : (c == t1 ? R.gq[q1] : R.gq[q2]);
+                            lagrange_dev<T>(R.x, N1, xc + dq[c], lv[c]);
+                        }
+                        T acc = 0, face = 0;
+#pragma unroll 1
+                        for (int jj = 0; jj < NC; ++jj) {
+                            int a0 = jj % N1, a1 = (jj / N1) % N1, a2 = D == 3 ? jj / (N1 * N1) : 0;
+                            T pv = lv[0][a0] * lv[1][a1];
+                            if (D == 3) pv *= lv[2][a2];
+                            acc += pv * su[lc][jj];
+                        }
+#pragma unroll 1
+                        for (int j = 0; j < NF; ++j) {
+                            int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
+                            T sv = R.S[q1][j1] * (D == 3 ? R.S[q2][j2] : T(1));
+                            face += sv * su[lc][compose<D, P>(k, layer, j)];
+                        }
+                        E = acc - face;
+                    }
+                    zeta = wq * E;
+                }
+                fa[lc][f][q] = zeta;
+            }
+        }
+        __syncthreads();
+        if (live && bnd) {
+#pragma unroll
+            for (int f = 0; f < NFACE; ++f) {
+                if (snb[lc][f] >= 0) continue;
+                int k = f >> 1, s = f & 1, m, j;
+                decompose<D, P>(i, k, m, j);
+                T sg = s == 1 ? T(1) : T(-1);
+                T ev = (m == (s ? P : 0)) ? T(1) : T(0);
+                T coef = -R.alpha * sg * R.g[s][m] + R.sigG * ev;
+                int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
+                T acc = 0;
+#pragma unroll 1
+                for (int q = 0; q < NF; ++q) {
+                    int q1 = q % N1, q2 = D == 3 ? q / N1 : 0;
+                    T sv = R.S[q1][j1] * (D == 3 ? R.S[q2][j2] : T(1));
+                    acc += fa[lc][f][q] * sv;
+                }
+                y += coef * acc;
+            }
+        }
+
+        // ---------------- output
+        y *= R.scale;
+        if (OP == OP_APPLY) {
+            if (live) out[(size_t)cell * NC + i] = y;
+        } else if (OP == OP_RESID) {
+            if (live) out[(size_t)cell * NC + i] = b[(size_t)cell * NC + i] - y;
+        } else {
+            __syncthreads();
+            if (live) sa[lc][i] = b[(size_t)cell * NC + i] - y;
+            __syncthreads();
+            if (live) {
+                int bi = a.bnd_of[cell];
+                T corr = 0;
+                if (bi < 0) {
+#pragma unroll 4
+                    for (int j = 0; j < NC; ++j) corr += sB[j * NC + i] * sa[lc][j];
+                } else {
+                    const T *Bt = a.Bbnd_t + (size_t)bi * NC * NC;
+#pragma unroll 2
+                    for (int j = 0; j < NC; ++j) corr += Bt[(size_t)j * NC + i] * sa[lc][j];
+                }
+                if (a.lw != nullptr && bi >= 0) {
+                    const T *U = a.lU + (size_t)bi * NC * 4;
+                    const T *V = a.lV + (size_t)bi * NC * 4;
+                    T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+#pragma unroll 1
+                    for (int j = 0; j < NC; ++j) {
+                        T r = sa[lc][j];
+                        v0 += V[j * 4 + 0] * r;
+                        v1 += V[j * 4 + 1] * r;
+                        v2 += V[j * 4 + 2] * r;
+                        v3 += V[j * 4 + 3] * r;
+                    }
+                    corr += U[i * 4 + 0] * v0 + U[i * 4 + 1] * v1 + U[i * 4 + 2] * v2 + U[i * 4 + 3] * v3;
+                    corr *= a.lw[bi];
+                }
+                out[(size_t)cell * NC + i] = su[lc][i] + R.omega * corr;
+            }
+        }
+    }  // batch loop
 }
 
 template <int D, int P, typename T>
@@ -367,6 +388,7 @@ static int launch_dp(int op, int cell0, int ncells, const T *x, T *y, const T *b
     if (ncells <= 0) return 0;
     using S = Sh<D, P>;
     int nb = (ncells + S::CPB - 1) / S::CPB;
+    if (op == OP_SMOOTH) nb = std::min(nb, 2048);
     if (op == OP_APPLY)
         hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_APPLY>), dim3(nb), dim3(256), 0, st, cell0, ncells, x, y, b, a, R);
     else if (op == OP_RESID)

@@ -132,8 +132,11 @@ int sbm_set_learned(sbm_problem *pb, const float *params, int width) {
     if (!D64.lw) {
         if ((rc = lalloc(pb, &D64.lw, nb)) || (rc = lalloc(pb, &D64.lU, (size_t)nb * nc * 4)) ||
             (rc = lalloc(pb, &D64.lV, (size_t)nb * nc * 4)) || (rc = lalloc(pb, &D32.lw, nb)) ||
-            (rc = lalloc(pb, &D32.lU, (size_t)nb * nc * 4)) || (rc = lalloc(pb, &D32.lV, (size_t)nb * nc * 4)) ||
-            (rc = lalloc(pb, &pb->lrn_X, (size_t)nb * n_in)) || (rc = lalloc(pb, &pb->lrn_O, (size_t)nb * n_out)) ||
+            (rc = lalloc(pb, &D32.lU, (size_t)nb * nc * 4)) || (rc = lalloc(pb, &D32.lV, (size_t)nb * nc * 4)))
+            return rc;
+    }
+    if (!pb->lrn_X) {
+        if ((rc = lalloc(pb, &pb->lrn_X, (size_t)nb * n_in)) || (rc = lalloc(pb, &pb->lrn_O, (size_t)nb * n_out)) ||
             (rc = lalloc(pb, &pb->lrn_wbuf, mlp_infer_wbuf_elems(n_out))))
             return rc;
     }
@@ -197,14 +200,14 @@ int sbm_mlp_forward(int fp64, int n_in, int width, int n_out, int batch, const v
     return rc ? SBM_EDEVICE : SBM_OK;
 }
 
-int sbm_mlp_loss_grad(int fp64, int batch, int n_cell, double omega, const void *O, const void *R, const void *BR,
-                      const void *E, void *dO, void *loss_s, void *loss, void *stream) {
+int sbm_mlp_loss_grad(int fp64, int batch, int n_cell, int train_uv, double omega, const void *O, const void *R,
+                      const void *BR, const void *E, void *dO, void *loss_s, void *loss, void *stream) {
     if (batch < 1 || n_cell < 1 || n_cell > 64 || !O || !R || !BR || !E || !dO || !loss_s || !loss) return SBM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    int rc = fp64 ? mlp_loss_grad<double>(batch, n_cell, omega, (const double *)O, (const double *)R,
+    int rc = fp64 ? mlp_loss_grad<double>(batch, n_cell, train_uv, omega, (const double *)O, (const double *)R,
                                           (const double *)BR, (const double *)E, (double *)dO, (double *)loss_s,
                                           (double *)loss, st)
-                  : mlp_loss_grad<float>(batch, n_cell, omega, (const float *)O, (const float *)R, (const float *)BR,
+                  : mlp_loss_grad<float>(batch, n_cell, train_uv, omega, (const float *)O, (const float *)R, (const float *)BR,
                                          (const float *)E, (float *)dO, (float *)loss_s, (float *)loss, st);
     return rc ? SBM_EDEVICE : SBM_OK;
 }

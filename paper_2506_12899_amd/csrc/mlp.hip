@@ -103,7 +103,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // One wave per sample.  O: [S][n_out], n_out = 1 + 2*nc*rank (rank = 4).
 template <typename T>
-__global__ __launch_bounds__(64) void loss_grad_kernel(int S, int nc, T omega, const T *__restrict__ O,
+__global__ __launch_bounds__(64) void loss_grad_kernel(int S, int nc, int train_uv, T omega, const T *__restrict__ O,
                                                        const T *__restrict__ R, const T *__restrict__ BR,
                                                        const T *__restrict__ E, T *__restrict__ dO,
                                                        T *__restrict__ loss_s) {
@@ -126,17 +126,19 @@ __global__ __launch_bounds__(64) void loss_grad_kernel(int S, int nc, T omega, c
     T w = T(2) * sig;
     T res = on ? omega * w * P - e : T(0);
     T ne = wave_sum(e * e);
-    T ls = wave_sum(res * res) / ne;
-    T g = T(2) * res / ne / T(S);
+    T inv_ne = ne > T(0) ? T(1) / ne : T(0);  // a zero-error sample contributes nothing
+    T ls = wave_sum(res * res) * inv_ne;
+    T g = T(2) * res * inv_ne / T(S);
     T dw = omega * wave_sum(g * P);
     T dP = omega * w * g;
     T *d = dO + (size_t)s * n_out;
     T dq[4];
     for (int a = 0; a < 4; ++a) dq[a] = wave_sum(dP * U[a]);
     if (on) {
+        // train_uv = 0 trains the relaxation weight only (U, V gradients zero)
         for (int a = 0; a < 4; ++a) {
-            d[1 + i * 4 + a] = dP * q[a];
-            d[1 + 4 * nc + i * 4 + a] = dq[a] * r;
+            d[1 + i * 4 + a] = train_uv ? dP * q[a] : T(0);
+            d[1 + 4 * nc + i * 4 + a] = train_uv ? dq[a] * r : T(0);
         }
     }
     if (i == 0) {
@@ -242,10 +244,11 @@ int mlp_backward(int n_in, int w, int n_out, int S, const T *p, const T *X, cons
 }
 
 template <typename T>
-int mlp_loss_grad(int S, int nc, double omega, const T *O, const T *R, const T *BR, const T *E, T *dO, T *loss_s,
-                  T *loss, hipStream_t st) {
+int mlp_loss_grad(int S, int nc, int train_uv, double omega, const T *O, const T *R, const T *BR, const T *E, T *dO,
+                  T *loss_s, T *loss, hipStream_t st) {
     if (S <= 0 || nc > 64) return -1;
-    hipLaunchKernelGGL((loss_grad_kernel<T>), dim3(S), dim3(64), 0, st, S, nc, (T)omega, O, R, BR, E, dO, loss_s);
+    hipLaunchKernelGGL((loss_grad_kernel<T>), dim3(S), dim3(64), 0, st, S, nc, train_uv, (T)omega, O, R, BR, E, dO,
+                       loss_s);
     hipLaunchKernelGGL((mean_kernel<T>), dim3(1), dim3(256), 0, st, S, loss_s, loss);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -265,9 +268,9 @@ template int mlp_backward<float>(int, int, int, int, const float *, const float 
                                  const float *, float *, float *, float *, hipStream_t);
 template int mlp_backward<double>(int, int, int, int, const double *, const double *, const double *, const double *,
                                   const double *, double *, double *, double *, hipStream_t);
-template int mlp_loss_grad<float>(int, int, double, const float *, const float *, const float *, const float *, float *,
+template int mlp_loss_grad<float>(int, int, int, double, const float *, const float *, const float *, const float *, float *,
                                   float *, float *, hipStream_t);
-template int mlp_loss_grad<double>(int, int, double, const double *, const double *, const double *, const double *,
+template int mlp_loss_grad<double>(int, int, int, double, const double *, const double *, const double *, const double *,
                                    double *, double *, double *, hipStream_t);
 
 // --------------------------------------------------------------------------

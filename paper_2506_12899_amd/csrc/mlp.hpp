@@ -11,7 +11,7 @@ template <typename T>
 int mlp_backward(int n_in, int w, int n_out, int S, const T *p, const T *X, const T *H1, const T *H2, const T *dO,
                  T *grads, T *dH, T *work, hipStream_t st);
 template <typename T>
-int mlp_loss_grad(int S, int nc, double omega, const T *O, const T *R, const T *BR, const T *E, T *dO, T *loss_s,
+int mlp_loss_grad(int S, int nc, int train_uv, double omega, const T *O, const T *R, const T *BR, const T *E, T *dO, T *loss_s,
                   T *loss, hipStream_t st);
 int adam_step(int n, float *p, const float *g, float *m, float *v, int t, float lr, float b1, float b2, float eps,
               hipStream_t st);

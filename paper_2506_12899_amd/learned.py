@@ -7,10 +7,11 @@ runs through sbm_set_learned (BF16 on the matrix cores).  Torch provides device
 memory only.
 
 Data protocol (per seeded training geometry, p = 3, 3D): x* ~ N(0, 1), b = A x*,
-z = 0; for a few outer iterations, before each finest-level colour update of
-the pre-smoothing step the boundary cells of that colour contribute the pair
-(e_K = x*_K - z_K, r_K = (b - A z)_K) together with B_K r_K and the cell's
-features; then z += V-cycle(b - A z).
+z = 0 (a white-noise error, the part a smoother must remove); before each
+finest-level colour update of the pre-smoothing step the boundary cells of
+that colour contribute the pair (e_K = x*_K - z_K, r_K = (b - A z)_K)
+together with B_K r_K and the cell's features; optional further outer
+iterations continue with z += V-cycle(b - A z).
 
 Checkpoint format (little-endian): magic b"SBMMLP01", int32 n_in, width,
 n_out, n_cell, int64 step, then params, Adam m, Adam v as float32.
@@ -35,8 +36,9 @@ def _p(t):
 class MLP:
     """Flat-parameter MLP trained with the library's kernels."""
 
-    def __init__(self, n_in, n_cell, width=64, rank=4, seed=0, device="cuda", omega=0.8):
+    def __init__(self, n_in, n_cell, width=64, rank=4, seed=0, device="cuda", omega=0.8, train_uv=True):
         self.n_in, self.width, self.n_cell = n_in, width, n_cell
+        self.train_uv = bool(train_uv)
         self.n_out = 1 + 2 * n_cell * rank
         self.omega = omega
         self.device = device
@@ -75,7 +77,8 @@ class MLP:
         S = X.shape[0]
         ws = self.forward(X, params)
         L = N.lib()
-        N.check(L.sbm_mlp_loss_grad(fp64, S, self.n_cell, self.omega, _p(ws["O"]), _p(R), _p(BR), _p(E),
+        N.check(L.sbm_mlp_loss_grad(fp64, S, self.n_cell, int(self.train_uv), self.omega, _p(ws["O"]), _p(R), _p(BR),
+                                    _p(E),
                                     _p(ws["dO"]), _p(ws["loss_s"]), _p(ws["loss"]), None))
         N.check(L.sbm_mlp_backward(fp64, self.n_in, self.width, self.n_out, S, _p(params), _p(X), _p(ws["H1"]),
                                    _p(ws["H2"]), _p(ws["dO"]), _p(ws["grads"]), _p(ws["dH"]), _p(ws["work"]), None))
@@ -150,34 +153,47 @@ def boundary_samples(pb, r, e):
     return R, BR, E
 
 
-def generate(problem_factory, seeds, n, p=3, outer=3, device="cuda", log=print):
-    """Training samples from the method's own smoothing on seeded geometries."""
+def generate(problem_factory, seeds, n, p=3, outer=1, draws=4, device="cuda", log=print):
+    """Training samples from the method's own smoothing on seeded geometries.
+
+    For each geometry, `draws` random exact solutions x* (white-noise initial
+    error) and `outer` outer iterations; before each finest-level colour
+    update of the pre-smoothing step the boundary cells of that colour give a
+    sample."""
     Xs, Rs, BRs, Es = [], [], [], []
     for s in seeds:
         geo = workloads.training_geometry(s)
         pb = problem_factory(geo, n, p)
         cells, F = boundary_info(pb)
         if len(cells) == 0:
+            pb.close()
             continue
         n_col0 = pb.layout.n_colour0
         lf = pb.n_levels - 1
-        g = torch.Generator(device="cpu").manual_seed(10_000 + s)
-        xs = torch.randn(pb.n_dofs, dtype=torch.float64, generator=g).to(device)
-        b = pb.apply(xs)
-        z = torch.zeros_like(b)
         Ft = torch.from_numpy(F).to(device)
         col = torch.from_numpy((cells >= n_col0).astype(np.int64)).to(device)
-        for _ in range(outer):
-            for c in (0, 1, 1, 0):
-                r = b - pb.apply(z)
-                R, BR, E = boundary_samples(pb, r, xs - z)
-                sel = (col == c) & (torch.linalg.vector_norm(E, dim=1) > 0)
-                Xs.append(Ft[sel])
-                Rs.append(R[sel])
-                BRs.append(BR[sel])
-                Es.append(E[sel])
-                pb.colour_update(lf, c, b, z)
-            z = z + pb.vcycle(b - pb.apply(z))
+        for dr in range(draws):
+            g = torch.Generator(device="cpu").manual_seed(10_000 + 97 * s + dr)
+            xs = torch.randn(pb.n_dofs, dtype=torch.float64, generator=g).to(device)
+            b = pb.apply(xs)
+            z = torch.zeros_like(b)
+            for it in range(outer):
+                for c in (0, 1, 1, 0):
+                    r = b - pb.apply(z)
+                    R, BR, E = boundary_samples(pb, r, xs - z)
+                    # the loss is invariant to a per-sample scale of (r, B r, e): scale
+                    # each sample to |e| = 1 in FP64 before it is stored in FP32
+                    ne = torch.linalg.vector_norm(E, dim=1)
+                    ok = torch.isfinite(ne) & (ne > 0) & torch.isfinite(R).all(1) & torch.isfinite(BR).all(1)
+                    sel = (col == c) & ok
+                    sc = 1.0 / ne[sel, None]
+                    Xs.append(Ft[sel])
+                    Rs.append(R[sel] * sc)
+                    BRs.append(BR[sel] * sc)
+                    Es.append(E[sel] * sc)
+                    pb.colour_update(lf, c, b, z)
+                if it + 1 < outer:
+                    z = z + pb.vcycle(b - pb.apply(z))
         pb.close()
         log(f"[learned] geometry {s}: {len(cells)} boundary cells")
     return (torch.cat(Xs).float(), torch.cat(Rs).float(), torch.cat(BRs).float(), torch.cat(Es).float())
@@ -189,6 +205,10 @@ def train(mlp, data, epochs=20, batch=4096, lr=1e-3, seed=0, log=print, time_bud
     g = torch.Generator(device="cpu").manual_seed(seed)
     hist = []
     t0 = time.time()
+    n0 = min(S, 8 * batch)
+    loss0, _ = mlp.loss_grad(X[:n0].contiguous(), R[:n0].contiguous(), BR[:n0].contiguous(), E[:n0].contiguous())
+    log(f"[learned] initial loss (plain smoother) {float(loss0.item()):.5f}")
+    hist.append(float(loss0.item()))
     for ep in range(epochs):
         perm = torch.randperm(S, generator=g).to(X.device)
         tot, nb = 0.0, 0

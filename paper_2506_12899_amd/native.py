@@ -78,7 +78,7 @@ SIGNATURES = [
     ("sbm_set_learned_arrays", C.c_int, [_VP] + [C.POINTER(C.c_double)] * 3),
     ("sbm_use_learned", C.c_int, [_VP, C.c_int]),
     ("sbm_mlp_forward", C.c_int, [C.c_int] * 5 + [_VP] * 6),
-    ("sbm_mlp_loss_grad", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double] + [_VP] * 8),
+    ("sbm_mlp_loss_grad", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double] + [_VP] * 8),
     ("sbm_mlp_work_elems", C.c_longlong, [C.c_int] * 4),
     ("sbm_mlp_backward", C.c_int, [C.c_int] * 5 + [_VP] * 9),
     ("sbm_adam", C.c_int, [C.c_int, _VP, _VP, _VP, _VP, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, _VP]),
