@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--max-iter", type=int, default=300, help="FGMRES iteration cap (failure beyond it)")
+    ap.add_argument("--profile-apply", action="store_true", help="only time finest-level applies (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -107,6 +108,19 @@ def main():
     x = torch.empty_like(b)
     print(f"[bench] {prob.name}: {pb.n_dofs} DoFs, {pb.n_levels} levels, setup {setup_s:.1f} s", file=sys.stderr,
           flush=True)
+    if args.profile_apply:
+        # finest-level applies only (FP64 then FP32), for kernel traces and counters
+        ta64 = time_apply(pb, torch, False, args.apply_reps, warm=2)
+        ta32 = time_apply(pb, torch, True, args.apply_reps, warm=2)
+        # a plain 256 MiB device copy: the reference for the HBM byte counters
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": prob.name, "n_dofs": int(pb.n_dofs), "reps": args.apply_reps,
+                          "apply_us_fp64": ta64 * 1e6, "apply_us_fp32": ta32 * 1e6,
+                          "bytes_fp64": apply_bytes(pb, False), "bytes_fp32": apply_bytes(pb, True)}), flush=True)
+        return
 
     def run(fp32, steps, warmup):
         pb.set_vcycle_fp32(fp32)

@@ -77,7 +77,10 @@ typedef struct {
                              (Sec. 2.1), 1 = cell polynomial evaluated at x~ + d (default 1) */
     double omega;         /* smoother relaxation (default 1 for p <= 2, 0.8 for p = 3)        */
     int nu_pre, nu_post;  /* SSOR steps before / after the coarse correction (default 1, 1)   */
-    int coarse_min;       /* halve n while n is even and n/2 >= coarse_min (default 3)        */
+    int coarse_min;       /* geometric coarsening (p = 1) halves n while n is even,           */
+    int coarse_dofs;      /* n/2 >= coarse_min (default 3) and the level still has more than  */
+                          /* coarse_dofs active DoFs (default 1024); the last level is solved */
+                          /* with a dense inverse (at most 4096 DoFs)                         */
     int vcycle_fp32;      /* sbm_solve: 0 = FP64 V-cycle, 1 = FP32 V-cycle (default 0)        */
     int allow_singular;   /* 1: shift near-singular blocks by 1e-10 |D_K| instead of failing  */
     int device;           /* HIP device ordinal (default 0); < 0 = host-only setup for tests:

@@ -11,7 +11,9 @@ Test infrastructure only.  Follows Sec. 3 of the paper:
     (fine nodes take the coarse polynomial's value), restriction = transpose.
 
 Readings (listed in the design notes):
-  * coarsening: halve n while n is even and n/2 >= coarse_min (3);
+  * coarsening: halve n while n is even, n/2 >= coarse_min (3) and the level
+    still has more than coarse_dofs (1024) active DoFs (the coarse solver and
+    coarsest mesh are not specified for the experiments);
   * the smoother visits the two colours (i+j+k mod 2) in the order 0,1,1,0 per
     step; cells of one colour do not couple, so a colour is updated at once;
   * omega = 1 for p <= 2 and 0.8 for p = 3 on every level;
@@ -27,7 +29,7 @@ from . import basis, dg
 
 
 def level_shapes(n, p, coarse_min=3):
-    """(n, p) of every level, finest first."""
+    """(n, p) of every level by the mesh rule alone, finest first."""
     out = [(n, q) for q in range(p, 0, -1)]
     while n % 2 == 0 and n // 2 >= coarse_min:
         n //= 2
@@ -40,9 +42,17 @@ def default_omega(p):
 
 
 class Hierarchy:
-    def __init__(self, geom, d, n, p, coarse_min=3, omega=None, nu_pre=1, nu_post=1, **kw):
-        shapes = level_shapes(n, p, coarse_min)[::-1]          # coarsest first
-        self.levels = [dg.Level(geom, d, nn, pp, **kw) for nn, pp in shapes]
+    """Levels coarsest first.  Geometric coarsening (p = 1) continues while n is
+    even, n/2 >= coarse_min and the current level has more than coarse_dofs
+    active DoFs; the last level is solved exactly."""
+
+    def __init__(self, geom, d, n, p, coarse_min=3, coarse_dofs=1024, omega=None, nu_pre=1, nu_post=1, **kw):
+        fine_first = [dg.Level(geom, d, n, q, **kw) for q in range(p, 0, -1)]
+        nn = n
+        while nn % 2 == 0 and nn // 2 >= coarse_min and fine_first[-1].n_dofs > coarse_dofs:
+            nn //= 2
+            fine_first.append(dg.Level(geom, d, nn, 1, **kw))
+        self.levels = fine_first[::-1]
         self.d = d
         self.omega = default_omega(p) if omega is None else float(omega)
         self.nu_pre, self.nu_post = nu_pre, nu_post

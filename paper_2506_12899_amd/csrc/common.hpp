@@ -106,6 +106,8 @@ struct DevLevel {
     int *nbr = nullptr;       // n_act * 2d
     int *bnd_of = nullptr;    // n_act
     int *bnd_cells = nullptr; // n_bnd
+    int *batch_start = nullptr;  // colour-interleaved batch table (see CellArgs)
+    int nbatch = 0;
     T *shift = nullptr;       // n_surr * nf * d, reference units d / h
     T *Bint_t = nullptr;      // transposed shared inverse, [j][i]
     T *Bbnd_t = nullptr;      // n_bnd * nc*nc transposed inverses

@@ -13,7 +13,8 @@
 // normal derivative on the shared face, the shift part at the face Gauss points.
 //
 // Thread mapping: one thread per DoF, 64 / (p+1)^d cells per wave (a cell
-// never straddles a wave), 4 waves per block; cell data staged in LDS.  The
+// never straddles a wave, so the cell's threads exchange LDS data without
+// block barriers), 4 waves per block; cell data staged in LDS.  The
 // block index is remapped so that each of the 8 XCDs works on a contiguous
 // range of cells (neighbour traces then hit that XCD's L2).
 #include "kernels.hpp"
@@ -35,6 +36,16 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     // blocks are dispatched round-robin over the 8 XCDs; give XCD x a contiguous range
     int x = b & 7, q = nb >> 3, r = nb & 7;
     return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// The threads of one cell always sit in one wave, so data exchanged through
+// LDS between them needs no block barrier: LDS instructions of a wave complete
+// in order, and this only keeps the compiler from moving memory operations
+// across the exchange point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // DoF index of node (m along direction k, tangential index j) of a cell
@@ -103,28 +114,57 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
     const bool slot = lane < S::CPW * NC;
     const int lc = slot ? wave * S::CPW + lane / NC : 0;
     const int i = slot ? lane % NC : 0;
-    if (OP == OP_SMOOTH)
+    if (OP == OP_SMOOTH) {
         for (int t = threadIdx.x; t < NC * NC; t += blockDim.x) sB[t] = a.Bint_t[t];
+        __syncthreads();
+    }
     // Each block owns a contiguous chunk of cell batches (one batch per block
     // for the apply, several for the smoother so that sB is staged once per
     // chunk); the remap gives every XCD a contiguous range of cells.
-    const int nbatch = (ncells + CPB - 1) / CPB;
+    const int nbatch = a.batch_start != nullptr ? a.nbatch : (ncells + CPB - 1) / CPB;
     const int chunk = OP == OP_SMOOTH ? (nbatch + gridDim.x - 1) / gridDim.x : 1;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int bb0 = blk * chunk;
     const int bb1 = OP == OP_SMOOTH ? min(nbatch, bb0 + chunk) : bb0 + 1;
 #pragma unroll 1
     for (int bb = bb0; bb < bb1; ++bb) {
-        const int lcell = bb * CPB + lc;
-        const bool live = slot && lcell < ncells;
-        const int cell = cell0 + lcell;
-        __syncthreads();  // the previous batch is done with the LDS buffers
+        int bstart, bend;
+        if (a.batch_start != nullptr) {
+            bstart = a.batch_start[bb];
+            bend = min(bstart + CPB, bstart < a.split ? a.split : cell0 + ncells);
+        } else {
+            bstart = cell0 + bb * CPB;
+            bend = cell0 + ncells;
+        }
+        const int cell = bstart + lc;
+        const bool live = slot && cell < bend;
+        wave_sync();  // the previous batch is done with this wave's LDS slices
 
         if (live) {
             su[lc][i] = xin[(size_t)cell * NC + i];
             if (i < NFACE) snb[lc][i] = a.nbr[(size_t)cell * NFACE + i];
         }
-        __syncthreads();
+        wave_sync();
+
+        // neighbour data for the face couplings: the loads are issued here and
+        // consumed after the volume stage, so their latency overlaps it
+        constexpr int ITEMS = (NFACE * NF + NC - 1) / NC;
+        T raw[ITEMS][N1];
+        if (live) {
+#pragma unroll
+            for (int q = 0; q < ITEMS; ++q) {
+                int it = i + q * NC;
+                if (it < NFACE * NF) {
+                    int f = it / NF, j = it % NF, k = f >> 1;
+                    int nb = snb[lc][f];
+                    if (nb >= 0) {
+                        const T *un = xin + (size_t)nb * NC;
+#pragma unroll
+                        for (int m = 0; m < N1; ++m) raw[q][m] = un[compose<D, P>(k, m, j)];
+                    }
+                }
+            }
+        }
 
         // ---------------- volume + unshifted self terms (sum factorisation)
         T y = 0;
@@ -145,7 +185,7 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
             sa[lc][i] = am;
             sb[lc][i] = bt;
         }
-        __syncthreads();
+        wave_sync();
         if (D == 2) {
             if (live) {
 #pragma unroll
@@ -163,12 +203,12 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
                     bM += R.M[c1][m] * bv;
                 }
             }
-            __syncthreads();
+            wave_sync();
             if (live) {
                 sa[lc][i] = aM;
                 sb[lc][i] = aT + bM;
             }
-            __syncthreads();
+            wave_sync();
             if (live) {
                 int base = i - N1 * N1 * c2;
 #pragma unroll
@@ -179,18 +219,19 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
 
         // ---------------- interior-face couplings: neighbour trace and normal derivative
         if (live) {
-            for (int it = i; it < NFACE * NF; it += NC) {
-                int f = it / NF, j = it % NF, k = f >> 1, s = f & 1;
+#pragma unroll
+            for (int q = 0; q < ITEMS; ++q) {
+                int it = i + q * NC;
+                if (it >= NFACE * NF) break;
+                int f = it / NF, j = it % NF, s = f & 1;
                 int nb = snb[lc][f];
                 T va = 0, vb = 0;
                 if (nb >= 0) {
-                    const T *un = xin + (size_t)nb * NC;
-                    const int layer = s == 1 ? 0 : P;
                     const T *gN = R.g[s == 1 ? 0 : 1];
-                    T t = un[compose<D, P>(k, layer, j)];
+                    T t = s == 1 ? raw[q][0] : raw[q][P];
                     T dn = 0;
 #pragma unroll
-                    for (int m = 0; m < N1; ++m) dn += gN[m] * un[compose<D, P>(k, m, j)];
+                    for (int m = 0; m < N1; ++m) dn += gN[m] * raw[q][m];
                     T sg = s == 1 ? T(1) : T(-1);
                     va = T(-0.5) * sg * dn - R.sigF * t;
                     vb = T(0.5) * t;
@@ -199,7 +240,7 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
                 fb[lc][f][j] = vb;
             }
         }
-        __syncthreads();
+        wave_sync();
         // tangential mass along the first tangential direction
         if (live) {
             for (int it = i; it < NFACE * NF; it += NC) {
@@ -215,7 +256,7 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
                 gb[lc][f][j] = vb;
             }
         }
-        __syncthreads();
+        wave_sync();
         if (D == 3) {
             if (live) {
                 for (int it = i; it < NFACE * NF; it += NC) {
@@ -231,7 +272,7 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
                     fb[lc][f][j] = vb;
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
         if (live) {
 #pragma unroll
@@ -246,7 +287,7 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
                 y += ev * F1 + sg * R.g[s][m] * F2;
             }
         }
-        __syncthreads();
+        wave_sync();
 
         // ---------------- shift part of the Nitsche terms on surrogate faces
         bool bnd = false;
@@ -318,7 +359,7 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
                 fa[lc][f][q] = zeta;
             }
         }
-        __syncthreads();
+        wave_sync();
         if (live && bnd) {
 #pragma unroll
             for (int f = 0; f < NFACE; ++f) {
@@ -347,9 +388,9 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
         } else if (OP == OP_RESID) {
             if (live) out[(size_t)cell * NC + i] = b[(size_t)cell * NC + i] - y;
         } else {
-            __syncthreads();
+            wave_sync();
             if (live) sa[lc][i] = b[(size_t)cell * NC + i] - y;
-            __syncthreads();
+            wave_sync();
             if (live) {
                 int bi = a.bnd_of[cell];
                 T corr = 0;
@@ -387,7 +428,7 @@ static int launch_dp(int op, int cell0, int ncells, const T *x, T *y, const T *b
                      const KRef<T> &R, hipStream_t st) {
     if (ncells <= 0) return 0;
     using S = Sh<D, P>;
-    int nb = (ncells + S::CPB - 1) / S::CPB;
+    int nb = a.batch_start != nullptr ? a.nbatch : (ncells + S::CPB - 1) / S::CPB;
     if (op == OP_SMOOTH) nb = std::min(nb, 2048);
     if (op == OP_APPLY)
         hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_APPLY>), dim3(nb), dim3(256), 0, st, cell0, ncells, x, y, b, a, R);
@@ -512,17 +553,20 @@ template int launch_restrict<float>(int, int, int, int, int, const int *, const 
 template <typename T>
 __global__ __launch_bounds__(256) void dense_gemv_kernel(int n, const T *__restrict__ A, const T *__restrict__ x,
                                                          T *__restrict__ y) {
-    int row = blockIdx.x * blockDim.x + threadIdx.x;
+    // one wave per row: the lanes stride over the row (coalesced), then reduce
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (row >= n) return;
+    const T *a = A + (size_t)row * n;
     T acc = 0;
-    for (int j = 0; j < n; ++j) acc += A[(size_t)row * n + j] * x[j];
-    y[row] = acc;
+    for (int j = lane; j < n; j += 64) acc += a[j] * x[j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) y[row] = acc;
 }
 
 template <typename T>
 int launch_dense_gemv(int n, const T *A, const T *x, T *y, hipStream_t st) {
     if (n <= 0) return 0;
-    hipLaunchKernelGGL((dense_gemv_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, n, A, x, y);
+    hipLaunchKernelGGL((dense_gemv_kernel<T>), dim3((n + 3) / 4), dim3(256), 0, st, n, A, x, y);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template int launch_dense_gemv<double>(int, const double *, const double *, double *, hipStream_t);

@@ -15,7 +15,19 @@ struct CellArgs {
     const T *Bint_t;      // nc * nc, transposed
     const T *Bbnd_t;      // n_bnd * nc * nc, transposed
     const T *lw, *lU, *lV;  // learned correction (may be null)
+    // Optional batch table for whole-level operations: batch b covers the cells
+    // [batch_start[b], min(batch_start[b] + CPB, end of its colour)); colour 0
+    // ends at split.  The table interleaves the two colours by position so that
+    // the contiguous range of batches an XCD receives is one spatial region.
+    const int *batch_start;
+    int nbatch, split;
 };
+
+// cells per block of the cell kernels (4 waves, 64 / (p+1)^d cells per wave)
+inline int cells_per_block(int d, int p) {
+    int nc = d == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
+    return 4 * (64 / nc);
+}
 
 template <typename T>
 struct TransferArgs {

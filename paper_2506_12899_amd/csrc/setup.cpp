@@ -50,17 +50,6 @@ static void parallel_for(long long n, F f) {
     for (auto &t : th) t.join();
 }
 
-std::vector<std::pair<int, int>> level_shapes(int n, int p, int coarse_min) {
-    std::vector<std::pair<int, int>> s;
-    for (int q = p; q >= 1; --q) s.push_back({n, q});
-    while (n % 2 == 0 && n / 2 >= coarse_min) {
-        n /= 2;
-        s.push_back({n, 1});
-    }
-    std::reverse(s.begin(), s.end());  // coarsest first
-    return s;
-}
-
 // 1D self operator for a direction with face types (t0 at xi = 0, t1 at xi = 1)
 static void self_1d(const HostLevel &L, double alpha, int t0, int t1, double T[MAXN1][MAXN1]) {
     const Ref1D &r = L.ref;

@@ -9,7 +9,6 @@
 
 namespace sbm {
 
-std::vector<std::pair<int, int>> level_shapes(int n, int p, int coarse_min);
 int build_level(const Geometry &g, const sbm_options &o, int n, int p, HostLevel &L, std::string &err);
 void build_transfer(const HostLevel &Lc, HostLevel &Lf);
 void embedding_1d(const HostLevel &Lc, const HostLevel &Lf, double P1[2][MAXN1][MAXN1]);

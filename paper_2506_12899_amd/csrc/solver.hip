@@ -105,6 +105,19 @@ int upload_level(sbm_problem *pb, int l, DevLevel<T> &D) {
     if ((rc = upload(pb, &D.nbr, L.nbr.data(), L.nbr.size()))) return rc;
     if ((rc = upload(pb, &D.bnd_of, L.bnd_of.data(), L.bnd_of.size()))) return rc;
     if ((rc = upload(pb, &D.bnd_cells, L.bnd_cells.data(), L.bnd_cells.size()))) return rc;
+    {
+        // whole-level batches, the two colours merged by relative position
+        const int cpb = cells_per_block(L.d, L.p);
+        const int nb0 = (L.n_col0 + cpb - 1) / cpb, nb1 = (L.n_act - L.n_col0 + cpb - 1) / cpb;
+        std::vector<int> starts;
+        int i0 = 0, i1 = 0;
+        while (i0 < nb0 || i1 < nb1) {
+            bool take0 = i1 >= nb1 || (i0 < nb0 && (2.0 * i0 + 1.0) * nb1 <= (2.0 * i1 + 1.0) * nb0);
+            starts.push_back(take0 ? (i0++) * cpb : L.n_col0 + (i1++) * cpb);
+        }
+        D.nbatch = (int)starts.size();
+        if ((rc = upload(pb, &D.batch_start, starts.data(), starts.size()))) return rc;
+    }
     std::vector<double> sh(L.shifts.size());
     for (size_t i = 0; i < sh.size(); ++i) sh[i] = L.shifts[i] / L.h;
     if ((rc = upload(pb, &D.shift, sh.data(), sh.size()))) return rc;
@@ -161,6 +174,9 @@ CellArgs<T> cell_args(const DevLevel<T> &D, bool learned) {
     a.lw = learned ? D.lw : nullptr;
     a.lU = learned ? D.lU : nullptr;
     a.lV = learned ? D.lV : nullptr;
+    a.batch_start = nullptr;
+    a.nbatch = 0;
+    a.split = D.n_col0;
     return a;
 }
 
@@ -174,7 +190,10 @@ std::vector<DevLevel<float>> &devlevels<float>(sbm_problem *pb) { return pb->dev
 template <typename T>
 int level_apply(sbm_problem *pb, int l, int op, const T *x, T *y, const T *b) {
     auto &D = devlevels<T>(pb)[l];
-    KCHK(launch_cellop<T>(D.d, D.p, op, 0, D.n_act, x, y, b, cell_args(D, false), D.kref, pb->stream));
+    CellArgs<T> a = cell_args(D, false);
+    a.batch_start = D.batch_start;
+    a.nbatch = D.nbatch;
+    KCHK(launch_cellop<T>(D.d, D.p, op, 0, D.n_act, x, y, b, a, D.kref, pb->stream));
     return SBM_OK;
 }
 
@@ -216,6 +235,22 @@ const double *coarse_inv<double>(sbm_problem *pb) { return pb->coarse.Ainv64; }
 template <>
 const float *coarse_inv<float>(sbm_problem *pb) { return pb->coarse.Ainv32; }
 
+// One SSOR step: colours 0, 1, 1, 0.  With omega = 1 and the exact cell
+// inverses, the first colour-1 update zeroes the residual of every colour-1
+// cell, and nothing it depends on changes before the repeated colour-1 update
+// (cells of one colour do not couple), so that update adds zero up to rounding
+// and is skipped.  With omega != 1 or the learned correction it is kept.
+template <typename T>
+int ssor_step(sbm_problem *pb, int l, const T *b, T *z) {
+    const bool learned_here = pb->learned_on && l == (int)pb->levels.size() - 1;
+    const bool skip_repeat = pb->opt.omega == 1.0 && !learned_here;
+    int rc;
+    if ((rc = colour_update<T>(pb, l, 0, b, z))) return rc;
+    if ((rc = colour_update<T>(pb, l, 1, b, z))) return rc;
+    if (!skip_repeat && (rc = colour_update<T>(pb, l, 1, b, z))) return rc;
+    return colour_update<T>(pb, l, 0, b, z);
+}
+
 template <typename T>
 int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z) {
     auto &D = devlevels<T>(pb)[l];
@@ -234,16 +269,14 @@ int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z) {
     int rc;
     KCHK(launch_fill<T>((long long)D.n_act * D.nc, z, T(0), pb->stream));
     for (int s = 0; s < pb->opt.nu_pre; ++s)
-        for (int c : {0, 1, 1, 0})
-            if ((rc = colour_update<T>(pb, l, c, b, z))) return rc;
+        if ((rc = ssor_step<T>(pb, l, b, z))) return rc;
     if ((rc = level_apply<T>(pb, l, OP_RESID, z, D.r, b))) return rc;
     auto &Dc = devlevels<T>(pb)[l - 1];
     if ((rc = restrict_to<T>(pb, l, D.r, Dc.b))) return rc;
     if ((rc = vcycle_rec<T>(pb, l - 1, Dc.b, Dc.z))) return rc;
     if ((rc = prolong_add<T>(pb, l, Dc.z, z))) return rc;
     for (int s = 0; s < pb->opt.nu_post; ++s)
-        for (int c : {0, 1, 1, 0})
-            if ((rc = colour_update<T>(pb, l, c, b, z))) return rc;
+        if ((rc = ssor_step<T>(pb, l, b, z))) return rc;
     return SBM_OK;
 }
 
@@ -290,6 +323,7 @@ int sbm_default_options(int dim, int p, sbm_options *o) {
     o->nu_pre = 1;
     o->nu_post = 1;
     o->coarse_min = 3;
+    o->coarse_dofs = 1024;
     o->vcycle_fp32 = 0;
     o->allow_singular = 0;
     o->device = 0;
@@ -316,7 +350,8 @@ int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_pro
     else
         sbm_default_options(g->dim, p, &pb->opt);
     sbm_options &op = pb->opt;
-    if (!(op.hi > op.lo) || op.nu_pre < 0 || op.nu_post < 0 || op.coarse_min < 1 || (op.ext != 0 && op.ext != 1)) {
+    if (!(op.hi > op.lo) || op.nu_pre < 0 || op.nu_post < 0 || op.coarse_min < 1 || op.coarse_dofs < 0 ||
+        (op.ext != 0 && op.ext != 1)) {
         delete pb;
         return SBM_EINVAL;
     }
@@ -358,18 +393,33 @@ int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_pro
         return SBM_EDEVICE;
     }
     pb->stream = (hipStream_t)op.stream;
-    auto shapes = level_shapes(n, p, op.coarse_min);
-    pb->levels.resize(shapes.size());
-    for (size_t l = 0; l < shapes.size(); ++l) {
-        std::string err;
-        int rc = build_level(G, op, shapes[l].first, shapes[l].second, pb->levels[l], err);
-        if (rc) {
-            pb->last_error = err;
-            *out = pb;  // caller can read the message, must destroy
-            return rc;
+    // finest first: p-levels on the finest mesh, then halve n with p = 1 while
+    // n is even, n/2 >= coarse_min and the current level has more than
+    // coarse_dofs active DoFs
+    {
+        std::vector<HostLevel> f2c;
+        int nn = n;
+        for (int q = p;; ) {
+            f2c.emplace_back();
+            std::string err;
+            int rc = build_level(G, op, nn, q, f2c.back(), err);
+            if (rc) {
+                pb->last_error = err;
+                *out = pb;  // caller can read the message, must destroy
+                return rc;
+            }
+            if (q > 1) {
+                --q;
+                continue;
+            }
+            const HostLevel &Lc = f2c.back();
+            if (nn % 2 != 0 || nn / 2 < op.coarse_min || (long long)Lc.n_act * Lc.nc <= op.coarse_dofs) break;
+            nn /= 2;
         }
-        if (l > 0) build_transfer(pb->levels[l - 1], pb->levels[l]);
+        pb->levels.assign(f2c.rbegin(), f2c.rend());
     }
+    for (size_t l = 1; l < pb->levels.size(); ++l) build_transfer(pb->levels[l - 1], pb->levels[l]);
+    const size_t nlev = pb->levels.size();
     // coarsest dense matrix and its inverse
     const HostLevel &L0 = pb->levels[0];
     long long n0 = (long long)L0.n_act * L0.nc;
@@ -397,9 +447,9 @@ int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_pro
         *out = pb;
         return rc;
     }
-    pb->dev64.resize(shapes.size());
-    pb->dev32.resize(shapes.size());
-    for (size_t l = 0; l < shapes.size(); ++l) {
+    pb->dev64.resize(nlev);
+    pb->dev32.resize(nlev);
+    for (size_t l = 0; l < nlev; ++l) {
         if ((rc = upload_level<double>(pb, (int)l, pb->dev64[l])) || (rc = upload_level<float>(pb, (int)l, pb->dev32[l]))) {
             *out = pb;
             return rc;

@@ -481,3 +481,10 @@ def test_level_shapes():
     assert mg.level_shapes(32, 1) == [(32, 1), (16, 1), (8, 1), (4, 1)]
     assert mg.level_shapes(96, 3) == [(96, 3), (96, 2), (96, 1), (48, 1), (24, 1), (12, 1), (6, 1), (3, 1)]
     assert mg.level_shapes(128, 3)[-1] == (4, 1)
+    # the size rule stops at the first p = 1 level with at most coarse_dofs DoFs
+    disk = geometry.Balls([[0.0, 0.0]], [0.7])
+    H = mg.Hierarchy(disk, 2, 32, 2)
+    assert [(L.n, L.p) for L in H.levels] == [(16, 1), (32, 1), (32, 2)]
+    assert H.levels[1].n_dofs > 1024 >= H.levels[0].n_dofs
+    H = mg.Hierarchy(disk, 2, 32, 1, coarse_dofs=0)
+    assert [(L.n, L.p) for L in H.levels] == [(4, 1), (8, 1), (16, 1), (32, 1)]
