@@ -125,8 +125,7 @@ struct DevLevel {
 
 struct CoarseDev {
     int n = 0;
-    double *Ainv64 = nullptr;
-    float *Ainv32 = nullptr;
+    double *Ainv64 = nullptr;   // dense inverse, used by the FP64 and the FP32 cycle
 };
 
 }  // namespace sbm

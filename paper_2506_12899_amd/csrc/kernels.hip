@@ -114,9 +114,13 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
     const bool slot = lane < S::CPW * NC;
     const int lc = slot ? wave * S::CPW + lane / NC : 0;
     const int i = slot ? lane % NC : 0;
+    // Every global load is issued as early as its address is known, so that a
+    // batch costs three dependent memory round trips (cell data; neighbour
+    // traces, shift vectors and the boundary-cell inverse; the store) rather
+    // than one per stage: small levels are bound by this latency.
     if (OP == OP_SMOOTH) {
+        // staged here, first read after a block barrier in the output stage
         for (int t = threadIdx.x; t < NC * NC; t += blockDim.x) sB[t] = a.Bint_t[t];
-        __syncthreads();
     }
     // Each block owns a contiguous chunk of cell batches (one batch per block
     // for the apply, several for the smoother so that sB is staged once per
@@ -140,16 +144,25 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
         const bool live = slot && cell < bend;
         wave_sync();  // the previous batch is done with this wave's LDS slices
 
+        T bval = 0;
+        int bi = -1;
         if (live) {
             su[lc][i] = xin[(size_t)cell * NC + i];
             if (i < NFACE) snb[lc][i] = a.nbr[(size_t)cell * NFACE + i];
+            if (OP != OP_APPLY) bval = b[(size_t)cell * NC + i];
+            if (OP == OP_SMOOTH) bi = a.bnd_of[cell];
         }
         wave_sync();
 
-        // neighbour data for the face couplings: the loads are issued here and
-        // consumed after the volume stage, so their latency overlaps it
+        // Face items (face f, tangential index j) handled by this thread: the
+        // neighbour's nodes on the line through the face point (interior
+        // faces) or the shift vector at the face Gauss point (surrogate
+        // faces).  Loaded here, consumed after the volume stage.
         constexpr int ITEMS = (NFACE * NF + NC - 1) / NC;
+        constexpr bool PRE_B = NC <= 9;   // boundary-cell inverse column kept in registers
         T raw[ITEMS][N1];
+        T dqr[ITEMS][D];
+        T bcol[PRE_B ? NC : 1];
         if (live) {
 #pragma unroll
             for (int q = 0; q < ITEMS; ++q) {
@@ -161,8 +174,17 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
                         const T *un = xin + (size_t)nb * NC;
 #pragma unroll
                         for (int m = 0; m < N1; ++m) raw[q][m] = un[compose<D, P>(k, m, j)];
+                    } else {
+                        const T *dq = a.shift + ((size_t)(-nb - 1) * NF + j) * D;
+#pragma unroll
+                        for (int c = 0; c < D; ++c) dqr[q][c] = dq[c];
                     }
                 }
+            }
+            if (OP == OP_SMOOTH && PRE_B && bi >= 0) {
+                const T *Bt = a.Bbnd_t + (size_t)bi * NC * NC;
+#pragma unroll
+                for (int j = 0; j < (PRE_B ? NC : 1); ++j) bcol[j] = Bt[(size_t)j * NC + i];
             }
         }
 
@@ -296,13 +318,15 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
             for (int f = 0; f < NFACE; ++f) bnd |= snb[lc][f] < 0;
         }
         if (live && bnd) {
-            for (int it = i; it < NFACE * NF; it += NC) {
+#pragma unroll
+            for (int qi = 0; qi < ITEMS; ++qi) {
+                const int it = i + qi * NC;
+                if (it >= NFACE * NF) break;
                 int f = it / NF, q = it % NF, k = f >> 1, s = f & 1;
                 int nb = snb[lc][f];
                 T zeta = 0;
                 if (nb < 0) {
-                    int rec = -nb - 1;
-                    const T *dq = a.shift + ((size_t)rec * NF + q) * D;
+                    const T *dq = dqr[qi];
                     int q1 = q % N1, q2 = D == 3 ? q / N1 : 0;
                     T wq = R.w[q1] * (D == 3 ? R.w[q2] : T(1));
                     const int layer = s ? P : 0;
@@ -327,8 +351,11 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
                         }
                         int t1 = k == 0 ? 1 : 0;
                         int t2 = k == 2 ? 1 : 2;
-                        E = dq[k] * dk + dq[t1] * dt1;
-                        if (D == 3) E += dq[t2] * dt2;
+                        // components picked with selects: dq lives in registers
+                        const T dk_k = k == 0 ? dq[0] : (k == 1 ? dq[1] : dq[D - 1]);
+                        const T dk_t1 = t1 == 0 ? dq[0] : dq[1];
+                        E = dk_k * dk + dk_t1 * dt1;
+                        if (D == 3) E += (t2 == 1 ? dq[1] : dq[D - 1]) * dt2;
                     } else {
                         // cell polynomial at the shifted point minus its value at the face point
                         T lv[3][N1];
@@ -386,17 +413,20 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
         if (OP == OP_APPLY) {
             if (live) out[(size_t)cell * NC + i] = y;
         } else if (OP == OP_RESID) {
-            if (live) out[(size_t)cell * NC + i] = b[(size_t)cell * NC + i] - y;
+            if (live) out[(size_t)cell * NC + i] = bval - y;
         } else {
             wave_sync();
-            if (live) sa[lc][i] = b[(size_t)cell * NC + i] - y;
+            if (live) sa[lc][i] = bval - y;
+            if (bb == bb0) __syncthreads();   // sB staged (block-uniform branch)
             wave_sync();
             if (live) {
-                int bi = a.bnd_of[cell];
                 T corr = 0;
                 if (bi < 0) {
 #pragma unroll 4
                     for (int j = 0; j < NC; ++j) corr += sB[j * NC + i] * sa[lc][j];
+                } else if (PRE_B) {
+#pragma unroll
+                    for (int j = 0; j < (PRE_B ? NC : 1); ++j) corr += bcol[j] * sa[lc][j];
                 } else {
                     const T *Bt = a.Bbnd_t + (size_t)bi * NC * NC;
 #pragma unroll 2
@@ -457,6 +487,73 @@ template int launch_cellop<double>(int, int, int, int, int, const double *, doub
                                    const CellArgs<double> &, const KRef<double> &, hipStream_t);
 template int launch_cellop<float>(int, int, int, int, int, const float *, float *, const float *,
                                   const CellArgs<float> &, const KRef<float> &, hipStream_t);
+
+// First colour-0 update of a smoothing step that starts from z = 0: the
+// residual is b itself, so colour-0 cells get z_K = omega B_K b_K (with the
+// learned correction where present) and colour-1 cells z_K = 0.  One thread
+// per DoF; replaces clearing z plus a full colour-0 update.
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void smooth_zero_kernel(int n_act, int split, const T *__restrict__ b,
+                                                          T *__restrict__ z, CellArgs<T> a, T omega) {
+    constexpr int NC = Sh<D, P>::NC;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)n_act * NC) return;
+    const int cell = (int)(t / NC), i = (int)(t % NC);
+    T out = 0;
+    if (cell < split) {
+        const T *bc = b + (size_t)cell * NC;
+        const int bi = a.bnd_of[cell];
+        const T *Bt = bi < 0 ? a.Bint_t : a.Bbnd_t + (size_t)bi * NC * NC;
+        T corr = 0;
+#pragma unroll 4
+        for (int j = 0; j < NC; ++j) corr += Bt[(size_t)j * NC + i] * bc[j];
+        if (a.lw != nullptr && bi >= 0) {
+            const T *U = a.lU + (size_t)bi * NC * 4;
+            const T *V = a.lV + (size_t)bi * NC * 4;
+            T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+#pragma unroll 1
+            for (int j = 0; j < NC; ++j) {
+                T r = bc[j];
+                v0 += V[j * 4 + 0] * r;
+                v1 += V[j * 4 + 1] * r;
+                v2 += V[j * 4 + 2] * r;
+                v3 += V[j * 4 + 3] * r;
+            }
+            corr += U[i * 4 + 0] * v0 + U[i * 4 + 1] * v1 + U[i * 4 + 2] * v2 + U[i * 4 + 3] * v3;
+            corr *= a.lw[bi];
+        }
+        out = T(0) + omega * corr;
+    }
+    z[t] = out;
+}
+
+template <int D, int P, typename T>
+static int launch_sz(int n_act, int split, const T *b, T *z, const CellArgs<T> &a, T omega, hipStream_t st) {
+    long long n = (long long)n_act * Sh<D, P>::NC;
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL((smooth_zero_kernel<D, P, T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n_act,
+                       split, b, z, a, omega);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+int launch_smooth_zero(int d, int p, int n_act, int split, const T *b, T *z, const CellArgs<T> &a, T omega,
+                       hipStream_t st) {
+    if (d == 2) {
+        if (p == 1) return launch_sz<2, 1, T>(n_act, split, b, z, a, omega, st);
+        if (p == 2) return launch_sz<2, 2, T>(n_act, split, b, z, a, omega, st);
+        if (p == 3) return launch_sz<2, 3, T>(n_act, split, b, z, a, omega, st);
+    } else {
+        if (p == 1) return launch_sz<3, 1, T>(n_act, split, b, z, a, omega, st);
+        if (p == 2) return launch_sz<3, 2, T>(n_act, split, b, z, a, omega, st);
+        if (p == 3) return launch_sz<3, 3, T>(n_act, split, b, z, a, omega, st);
+    }
+    return -1;
+}
+template int launch_smooth_zero<double>(int, int, int, int, const double *, double *, const CellArgs<double> &,
+                                        double, hipStream_t);
+template int launch_smooth_zero<float>(int, int, int, int, const float *, float *, const CellArgs<float> &, float,
+                                       hipStream_t);
 
 // --------------------------------------------------------------------------
 // Transfers (Sec. 3.2): prolongation = embedding of the coarse cell polynomial
@@ -549,28 +646,29 @@ template int launch_restrict<float>(int, int, int, int, int, const int *, const 
                                     const TransferArgs<float> &, hipStream_t);
 
 // --------------------------------------------------------------------------
-// Coarsest level: z = A0^{-1} b with the dense inverse (one row per thread).
-template <typename T>
-__global__ __launch_bounds__(256) void dense_gemv_kernel(int n, const T *__restrict__ A, const T *__restrict__ x,
-                                                         T *__restrict__ y) {
+// Coarsest level: z = A0^{-1} b with the dense inverse, accumulated in the
+// matrix type TA (the FP32 cycle passes FP32 vectors and the FP64 inverse).
+template <typename TA, typename TX>
+__global__ __launch_bounds__(256) void dense_gemv_kernel(int n, const TA *__restrict__ A, const TX *__restrict__ x,
+                                                         TX *__restrict__ y) {
     // one wave per row: the lanes stride over the row (coalesced), then reduce
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (row >= n) return;
-    const T *a = A + (size_t)row * n;
-    T acc = 0;
-    for (int j = lane; j < n; j += 64) acc += a[j] * x[j];
+    const TA *a = A + (size_t)row * n;
+    TA acc = 0;
+    for (int j = lane; j < n; j += 64) acc += a[j] * (TA)x[j];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (lane == 0) y[row] = acc;
+    if (lane == 0) y[row] = (TX)acc;
 }
 
-template <typename T>
-int launch_dense_gemv(int n, const T *A, const T *x, T *y, hipStream_t st) {
+template <typename TA, typename TX>
+int launch_dense_gemv(int n, const TA *A, const TX *x, TX *y, hipStream_t st) {
     if (n <= 0) return 0;
-    hipLaunchKernelGGL((dense_gemv_kernel<T>), dim3((n + 3) / 4), dim3(256), 0, st, n, A, x, y);
+    hipLaunchKernelGGL((dense_gemv_kernel<TA, TX>), dim3((n + 3) / 4), dim3(256), 0, st, n, A, x, y);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
-template int launch_dense_gemv<double>(int, const double *, const double *, double *, hipStream_t);
-template int launch_dense_gemv<float>(int, const float *, const float *, float *, hipStream_t);
+template int launch_dense_gemv<double, double>(int, const double *, const double *, double *, hipStream_t);
+template int launch_dense_gemv<double, float>(int, const double *, const float *, float *, hipStream_t);
 
 // --------------------------------------------------------------------------
 template <typename T>
@@ -609,63 +707,219 @@ int launch_cast_f2d(long long n, const float *x, double *y, hipStream_t st) {
 }
 
 // --------------------------------------------------------------------------
-// FGMRES vector kernels (FP64).  Deterministic: fixed grid, per-block partial
-// sums, one reducing block.
-constexpr int RED_BLOCKS = 1024;
+// FGMRES vector kernels (FP64).
+//
+// Sums are deterministic: each block of a streaming kernel stores its partial
+// sums (plain stores), and the partials are added in one fixed order either
+// by the next streaming kernel, in every block (it needs the result to go on),
+// or by a small reduction kernel when only the host needs it.
+constexpr int GS_BLOCKS = 256;   // one 16-wave block per CU
+constexpr int GS_THREADS = 1024;
+constexpr int GS_WAVES = GS_THREADS / 64;
+constexpr int GS_MAXV = 32;      // sums per launch: up to 31 basis vectors plus one norm
 
-// partial[blk * m + i] = sum over the block's slice of V_i . w   (V_i = V + i * n)
-__global__ __launch_bounds__(256) void multidot_kernel(long long n, int m, const double *__restrict__ V,
-                                                       const double *__restrict__ w, double *__restrict__ partial) {
-    __shared__ double red[4][32];
-    double acc[32];
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// partial[blockIdx.x * nv + i] = sum over the block's threads of acc[i], i < nv
+// (NW waves per block)
+template <int NW>
+__device__ __forceinline__ void block_partials(const double (&acc)[GS_MAXV], int nv, double *partial) {
+    __shared__ double red[NW][GS_MAXV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < 32; ++i) acc[i] = 0.0;
-    long long st = (long long)gridDim.x * blockDim.x;
-    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
-        double wk = w[k];
-#pragma unroll
-        for (int i = 0; i < 32; ++i)
-            if (i < m) acc[i] += V[(size_t)i * n + k] * wk;
-    }
-    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < 32; ++i) {
-        if (i >= m) break;
-        double v = acc[i];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) red[wave][i] = v;
+    for (int i = 0; i < GS_MAXV; ++i) {
+        if (i < nv) {
+            double v = wave_sum(acc[i]);
+            if (lane == 0) red[wave][i] = v;
+        }
     }
     __syncthreads();
-    if (threadIdx.x < m)
-        partial[(size_t)blockIdx.x * m + threadIdx.x] =
-            red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-}
-
-// out[i] = sum_blk partial[blk * m + i]  (one block, fixed order)
-__global__ __launch_bounds__(256) void reduce_partials_kernel(int nblk, int m, const double *__restrict__ partial,
-                                                              double *__restrict__ out) {
-    __shared__ double red[256];
-    for (int i = 0; i < m; ++i) {
+    if ((int)threadIdx.x < nv) {
+        const int i = threadIdx.x;
         double v = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[(size_t)b * m + i];
-        red[threadIdx.x] = v;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[i] = red[0];
-        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < NW; ++w) v += red[w][i];
+        partial[(size_t)blockIdx.x * nv + i] = v;
     }
 }
 
-int launch_multidot(long long n, int m, const double *V, const double *w, double *partial, double *out,
-                    hipStream_t st) {
-    if (m <= 0 || m > 32) return -1;
-    long long want = (n + 255) / 256;
-    int nb = (int)std::max<long long>(1, std::min<long long>(want, RED_BLOCKS));
-    hipLaunchKernelGGL(multidot_kernel, dim3(nb), dim3(256), 0, st, n, m, V, w, partial);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, st, nb, m, partial, out);
+// dst[i] = sum_b partial[b * nv + i] over nblk <= GS_BLOCKS blocks, i < nv, in
+// one fixed order whatever the block size (lane l adds blocks l, l + 64, ...;
+// then a butterfly over the lanes; wave w of NW takes sums w, w + NW, ...).
+// dst may be LDS or global memory; the caller synchronises before reading it.
+template <int NW>
+__device__ __forceinline__ void sum_partials(const double *__restrict__ partial, int nblk, int nv, double *dst) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int PER_LANE = GS_BLOCKS / 64, PER_WAVE = GS_MAXV / NW;
+    double t[PER_WAVE][PER_LANE];
+#pragma unroll
+    for (int r = 0; r < PER_WAVE; ++r) {
+        const int i = wave + NW * r;
+#pragma unroll
+        for (int u = 0; u < PER_LANE; ++u) {
+            const int b = lane + 64 * u;
+            t[r][u] = i < nv && b < nblk ? partial[(size_t)b * nv + i] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < PER_WAVE; ++r) {
+        const int i = wave + NW * r;
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < PER_LANE; ++u) v += t[r][u];
+        v = wave_sum(v);
+        if (lane == 0 && i < nv) dst[i] = v;
+    }
+}
+
+static int gs_grid(long long n) {
+    return (int)std::max<long long>(1, std::min<long long>((n + GS_THREADS - 1) / GS_THREADS, GS_BLOCKS));
+}
+
+// The streaming kernels are instantiated for a bound MB >= m on the number of
+// basis vectors.  Rows i >= m read row m - 1 instead (a valid address, already
+// in cache) with a zero weight or an unused sum, so every load of an element
+// step is unconditional and all of them are in flight together.
+static int gs_bucket(int m) { return m == 0 ? 0 : m <= 4 ? 4 : m <= 8 ? 8 : m <= 16 ? 16 : 32; }
+// the 32-vector pass runs 512-thread blocks so that it has 256 registers per lane
+template <int MB>
+constexpr int gs_threads() { return MB > 16 ? 512 : GS_THREADS; }
+
+// partials of V_i . w (i < m) and of w . w (slot m)
+template <int MB>
+__global__ __launch_bounds__(gs_threads<MB>()) void gs_dots_kernel(long long n, int m, const double *__restrict__ V,
+                                                             const double *__restrict__ w, double *__restrict__ part) {
+    double acc[GS_MAXV];
+#pragma unroll
+    for (int i = 0; i < GS_MAXV; ++i) acc[i] = 0.0;
+    double ww = 0.0;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
+        const double wk = w[k];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) acc[i] += V[(size_t)(i < m ? i : m - 1) * n + k] * wk;
+        ww += wk * wk;
+    }
+#pragma unroll
+    for (int i = 0; i < GS_MAXV; ++i)
+        if (i == m) acc[i] = ww;
+    block_partials<gs_threads<MB>() / 64>(acc, m + 1, part);
+}
+
+// h = sums of the nblk_in x (m + 1) partials hpart (block 0 also stores all
+// m + 1 of them in hout); w <- w - sum_i h[i] V_i; partials of V_i . w (i < m)
+// and of w . w (slot m)
+template <int MB>
+__global__ __launch_bounds__(gs_threads<MB>()) void gs_axpy_dots_kernel(long long n, int m, const double *__restrict__ V,
+                                                                  const double *__restrict__ hpart, int nblk_in,
+                                                                  double *__restrict__ hout, double *__restrict__ w,
+                                                                  double *__restrict__ part) {
+    __shared__ double hs[GS_MAXV];
+    sum_partials<gs_threads<MB>() / 64>(hpart, nblk_in, m + 1, hs);
+    __syncthreads();
+    if (blockIdx.x == 0 && (int)threadIdx.x <= m) hout[threadIdx.x] = hs[threadIdx.x];
+    // up to 16 vectors the weights and the loaded elements stay in registers;
+    // beyond that the weights are read from LDS and the elements loaded again
+    // for the second sum (cache hits), which avoids spills
+    constexpr bool KEEP = MB <= 16;
+    if (!KEEP && (int)threadIdx.x < GS_MAXV && (int)threadIdx.x >= m) hs[threadIdx.x] = 0.0;
+    __syncthreads();
+    double hh[KEEP && MB > 0 ? MB : 1], acc[GS_MAXV];
+#pragma unroll
+    for (int i = 0; i < (KEEP ? MB : 0); ++i) hh[i] = i < m ? hs[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < GS_MAXV; ++i) acc[i] = 0.0;
+    double ww = 0.0;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
+        double vk[KEEP && MB > 0 ? MB : 1];
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const double v = V[(size_t)(i < m ? i : m - 1) * n + k];
+            if (KEEP) vk[i] = v;
+            s += (KEEP ? hh[i] : hs[i]) * v;
+        }
+        const double wk = w[k] - s;
+        w[k] = wk;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) acc[i] += (KEEP ? vk[i] : V[(size_t)(i < m ? i : m - 1) * n + k]) * wk;
+        ww += wk * wk;
+    }
+#pragma unroll
+    for (int i = 0; i < GS_MAXV; ++i)
+        if (i == m) acc[i] = ww;
+    block_partials<gs_threads<MB>() / 64>(acc, m + 1, part);
+}
+
+__global__ __launch_bounds__(GS_THREADS) void gs_reduce_kernel(const double *__restrict__ part, int nblk, int nv,
+                                                               double *__restrict__ out) {
+    sum_partials<GS_WAVES>(part, nblk, nv, out);
+}
+
+int launch_gs_dots(long long n, int m, const double *V, const double *w, double *part, hipStream_t st) {
+    if (m < 0 || m > GS_MAXV - 1 || n < 0) return -1;
+    const dim3 g(gs_grid(n)), bl(GS_THREADS), bl32(gs_threads<32>());
+    switch (gs_bucket(m)) {
+        case 0: hipLaunchKernelGGL(gs_dots_kernel<0>, g, bl, 0, st, n, m, V, w, part); break;
+        case 4: hipLaunchKernelGGL(gs_dots_kernel<4>, g, bl, 0, st, n, m, V, w, part); break;
+        case 8: hipLaunchKernelGGL(gs_dots_kernel<8>, g, bl, 0, st, n, m, V, w, part); break;
+        case 16: hipLaunchKernelGGL(gs_dots_kernel<16>, g, bl, 0, st, n, m, V, w, part); break;
+        default: hipLaunchKernelGGL(gs_dots_kernel<32>, g, bl32, 0, st, n, m, V, w, part);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_gs_axpy_dots(long long n, int m, const double *V, const double *hpart, double *hout, double *w,
+                        double *part, hipStream_t st) {
+    if (m < 1 || m > GS_MAXV - 1 || n < 0) return -1;
+    const int nb = gs_grid(n);
+    const dim3 g(nb), bl(GS_THREADS), bl32(gs_threads<32>());
+    switch (gs_bucket(m)) {
+        case 4: hipLaunchKernelGGL(gs_axpy_dots_kernel<4>, g, bl, 0, st, n, m, V, hpart, nb, hout, w, part); break;
+        case 8: hipLaunchKernelGGL(gs_axpy_dots_kernel<8>, g, bl, 0, st, n, m, V, hpart, nb, hout, w, part); break;
+        case 16: hipLaunchKernelGGL(gs_axpy_dots_kernel<16>, g, bl, 0, st, n, m, V, hpart, nb, hout, w, part); break;
+        default: hipLaunchKernelGGL(gs_axpy_dots_kernel<32>, g, bl32, 0, st, n, m, V, hpart, nb, hout, w, part);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_gs_reduce(long long n, int nv, const double *part, double *out, hipStream_t st) {
+    if (nv < 1 || nv > GS_MAXV) return -1;
+    hipLaunchKernelGGL(gs_reduce_kernel, dim3(1), dim3(GS_THREADS), 0, st, part, gs_grid(n), nv, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// v = (w - sum_i h[i] V_i) * inv
+template <int MB>
+__global__ __launch_bounds__(256) void gs_axpy_scale_kernel(long long n, int m, const double *__restrict__ V,
+                                                            const double *__restrict__ h, double inv,
+                                                            const double *__restrict__ w, double *__restrict__ v) {
+    double hh[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) hh[i] = i < m ? h[i] : 0.0;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) s += hh[i] * V[(size_t)(i < m ? i : m - 1) * n + k];
+        v[k] = (w[k] - s) * inv;
+    }
+}
+int launch_gs_axpy_scale(long long n, int m, const double *V, const double *h, double inv, const double *w, double *v,
+                         hipStream_t st) {
+    if (m < 1 || m > GS_MAXV - 1) return -1;
+    if (n <= 0) return 0;
+    const dim3 g((unsigned)std::min<long long>((n + 255) / 256, 8192)), bl(256);
+    switch (gs_bucket(m)) {
+        case 4: hipLaunchKernelGGL(gs_axpy_scale_kernel<4>, g, bl, 0, st, n, m, V, h, inv, w, v); break;
+        case 8: hipLaunchKernelGGL(gs_axpy_scale_kernel<8>, g, bl, 0, st, n, m, V, h, inv, w, v); break;
+        case 16: hipLaunchKernelGGL(gs_axpy_scale_kernel<16>, g, bl, 0, st, n, m, V, h, inv, w, v); break;
+        default: hipLaunchKernelGGL(gs_axpy_scale_kernel<32>, g, bl, 0, st, n, m, V, h, inv, w, v);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

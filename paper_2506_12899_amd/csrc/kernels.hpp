@@ -38,19 +38,33 @@ template <typename T>
 int launch_cellop(int d, int p, int op, int cell0, int ncells, const T *x, T *y, const T *b, const CellArgs<T> &a,
                   const KRef<T> &R, hipStream_t st);
 template <typename T>
+int launch_smooth_zero(int d, int p, int n_act, int split, const T *b, T *z, const CellArgs<T> &a, T omega,
+                       hipStream_t st);
+template <typename T>
 int launch_prolong(int d, int n_fine, int n1f, int n1c, const int *parent, const int *childpos, const T *zc, T *zf,
                    const TransferArgs<T> &tr, hipStream_t st);
 template <typename T>
 int launch_restrict(int d, int n_coarse, int n1f, int n1c, int nch, const int *children, const T *rf, T *bc,
                     const TransferArgs<T> &tr, hipStream_t st);
-template <typename T>
-int launch_dense_gemv(int n, const T *A, const T *x, T *y, hipStream_t st);
+template <typename TA, typename TX>
+int launch_dense_gemv(int n, const TA *A, const TX *x, TX *y, hipStream_t st);
 template <typename T>
 int launch_fill(long long n, T *x, T v, hipStream_t st);
 int launch_cast_d2f(long long n, const double *x, float *y, hipStream_t st);
 int launch_cast_f2d(long long n, const float *x, double *y, hipStream_t st);
-int launch_multidot(long long n, int m, const double *V, const double *w, double *partial, double *out,
-                    hipStream_t st);
+// Gram-Schmidt kernels.  Partial-sum buffers hold gs_partials_max() doubles;
+// the two passes of one Arnoldi step use two different buffers.
+constexpr int gs_partials_max() { return 256 * 32; }
+// part <- per-block partials of V_i . w (i < m) and w . w
+int launch_gs_dots(long long n, int m, const double *V, const double *w, double *part, hipStream_t st);
+// h = sums of hpart (also stored in hout[0..m]); w -= V h; part <- partials of V_i . w and w . w
+int launch_gs_axpy_dots(long long n, int m, const double *V, const double *hpart, double *hout, double *w,
+                        double *part, hipStream_t st);
+// out[0..nv) = sums of the partials left by a kernel above for vectors of length n
+int launch_gs_reduce(long long n, int nv, const double *part, double *out, hipStream_t st);
+// v = (w - V h) * inv
+int launch_gs_axpy_scale(long long n, int m, const double *V, const double *h, double inv, const double *w, double *v,
+                         hipStream_t st);
 int launch_multiaxpy(long long n, int m, double sign, const double *h, const double *V, double *w, hipStream_t st);
 int launch_scale(long long n, const double *nrm2, const double *w, double *v, hipStream_t st);
 

@@ -228,24 +228,23 @@ int prolong_add(sbm_problem *pb, int l, const T *zc, T *zf) {
     return SBM_OK;
 }
 
-template <typename T>
-const T *coarse_inv(sbm_problem *pb);
-template <>
-const double *coarse_inv<double>(sbm_problem *pb) { return pb->coarse.Ainv64; }
-template <>
-const float *coarse_inv<float>(sbm_problem *pb) { return pb->coarse.Ainv32; }
-
 // One SSOR step: colours 0, 1, 1, 0.  With omega = 1 and the exact cell
 // inverses, the first colour-1 update zeroes the residual of every colour-1
 // cell, and nothing it depends on changes before the repeated colour-1 update
 // (cells of one colour do not couple), so that update adds zero up to rounding
 // and is skipped.  With omega != 1 or the learned correction it is kept.
 template <typename T>
-int ssor_step(sbm_problem *pb, int l, const T *b, T *z) {
+int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false) {
     const bool learned_here = pb->learned_on && l == (int)pb->levels.size() - 1;
     const bool skip_repeat = pb->opt.omega == 1.0 && !learned_here;
     int rc;
-    if ((rc = colour_update<T>(pb, l, 0, b, z))) return rc;
+    if (from_zero) {
+        auto &D = devlevels<T>(pb)[l];
+        KCHK(launch_smooth_zero<T>(D.d, D.p, D.n_act, D.n_col0, b, z, cell_args(D, learned_here && D.lw != nullptr),
+                                   D.kref.omega, pb->stream));
+    } else if ((rc = colour_update<T>(pb, l, 0, b, z))) {
+        return rc;
+    }
     if ((rc = colour_update<T>(pb, l, 1, b, z))) return rc;
     if (!skip_repeat && (rc = colour_update<T>(pb, l, 1, b, z))) return rc;
     return colour_update<T>(pb, l, 0, b, z);
@@ -255,20 +254,19 @@ template <typename T>
 int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z) {
     auto &D = devlevels<T>(pb)[l];
     if (l == 0) {
-        if (sizeof(T) == sizeof(double)) {
-            KCHK(launch_dense_gemv<T>(pb->coarse.n, coarse_inv<T>(pb), b, z, pb->stream));
-        } else {
-            // the coarsest problem is tiny and can be badly conditioned: solve it in FP64
-            auto &D64 = pb->dev64[0];
-            KCHK(launch_cast_f2d(pb->coarse.n, (const float *)b, D64.b, pb->stream));
-            KCHK(launch_dense_gemv<double>(pb->coarse.n, pb->coarse.Ainv64, D64.b, D64.z, pb->stream));
-            KCHK(launch_cast_d2f(pb->coarse.n, D64.z, (float *)z, pb->stream));
-        }
+        // the coarsest problem is tiny and can be badly conditioned: the FP32
+        // cycle also solves it with the FP64 inverse
+        KCHK((launch_dense_gemv<double, T>(pb->coarse.n, pb->coarse.Ainv64, b, z, pb->stream)));
         return SBM_OK;
     }
     int rc;
-    KCHK(launch_fill<T>((long long)D.n_act * D.nc, z, T(0), pb->stream));
-    for (int s = 0; s < pb->opt.nu_pre; ++s)
+    if (pb->opt.nu_pre > 0) {
+        // z starts at zero: the first colour-0 update needs no operator application
+        if ((rc = ssor_step<T>(pb, l, b, z, true))) return rc;
+    } else {
+        KCHK(launch_fill<T>((long long)D.n_act * D.nc, z, T(0), pb->stream));
+    }
+    for (int s = 1; s < pb->opt.nu_pre; ++s)
         if ((rc = ssor_step<T>(pb, l, b, z))) return rc;
     if ((rc = level_apply<T>(pb, l, OP_RESID, z, D.r, b))) return rc;
     auto &Dc = devlevels<T>(pb)[l - 1];
@@ -442,8 +440,7 @@ int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_pro
         return SBM_OK;
     }
     int rc;
-    if ((rc = upload(pb, &pb->coarse.Ainv64, Ainv.data(), Ainv.size())) ||
-        (rc = upload(pb, &pb->coarse.Ainv32, Ainv.data(), Ainv.size()))) {
+    if ((rc = upload(pb, &pb->coarse.Ainv64, Ainv.data(), Ainv.size()))) {
         *out = pb;
         return rc;
     }
@@ -704,15 +701,18 @@ int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, in
     int rc;
     if (pb->ws_restart < m) {
         if ((rc = dalloc(pb, &pb->V, (size_t)(m + 1) * n)) || (rc = dalloc(pb, &pb->Z, (size_t)m * n)) ||
-            (rc = dalloc(pb, &pb->w, (size_t)n)) || (rc = dalloc(pb, &pb->red, (size_t)1024 * 32)) ||
+            (rc = dalloc(pb, &pb->w, (size_t)n)) || (rc = dalloc(pb, &pb->red, (size_t)2 * sbm::gs_partials_max())) ||
             (rc = dalloc(pb, &pb->hdev, (size_t)128)))
             return rc;
         pb->ws_restart = m;
     }
     double *V = pb->V, *Z = pb->Z, *w = pb->w, *hd = pb->hdev, *hp = pb->pinned;
+    // two partial-sum buffers: the passes of one Arnoldi step alternate between them
+    double *pa = pb->red, *pq = pb->red + sbm::gs_partials_max();
     const bool f32 = pb->opt.vcycle_fp32 != 0;
     // ||b||
-    KCHK(launch_multidot(n, 1, b, b, pb->red, hd, s));
+    KCHK(launch_gs_dots(n, 0, nullptr, b, pa, s));
+    KCHK(launch_gs_reduce(n, 1, pa, hd, s));
     HIPCHK(hipMemcpyAsync(hp, hd, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const double nb = std::sqrt(hp[0]);
@@ -734,7 +734,8 @@ int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, in
     int status = SBM_NOT_CONVERGED;
     for (;;) {
         hp[0] = beta * beta;
-        // device scratch hd: [0,32) CGS pass 1, [32,64) pass 2, 64 norm^2, [96,126) y, 127 beta^2
+        // device scratch hd: [0,32) CGS pass 1, [32,64) pass 2, [64,96) explicit norm, [96,126) y,
+        // 127 beta^2
         HIPCHK(hipMemcpyAsync(hd + 127, hp, sizeof(double), hipMemcpyHostToDevice, s));
         KCHK(launch_scale(n, hd + 127, w, V, s));
         std::fill(H.begin(), H.end(), 0.0);
@@ -752,18 +753,38 @@ int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, in
                 if ((rc = vcycle_rec<double>(pb, lf, vj, zj))) return rc;
             }
             if ((rc = level_apply<double>(pb, lf, OP_APPLY, zj, w, nullptr))) return rc;
-            // CGS2
-            KCHK(launch_multidot(n, j + 1, V, w, pb->red, hd, s));
-            KCHK(launch_multiaxpy(n, j + 1, -1.0, hd, V, w, s));
-            KCHK(launch_multidot(n, j + 1, V, w, pb->red, hd + 32, s));
-            KCHK(launch_multiaxpy(n, j + 1, -1.0, hd + 32, V, w, s));
-            KCHK(launch_multidot(n, 1, w, w, pb->red, hd + 64, s));
-            KCHK(launch_scale(n, hd + 64, w, V + (size_t)(j + 1) * n, s));
-            HIPCHK(hipMemcpyAsync(hp, hd, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
+            // Classical Gram-Schmidt, applied twice.  Pass 1 projections h1 = V^T w;
+            // the second kernel adds up h1, subtracts it and forms the pass-2
+            // projections h2 = V^T w' with |w'|^2 in the same sweep.  The pass-2 subtraction is
+            // fused with the normalisation, the norm following from
+            // |w''|^2 = |w'|^2 - |h2|^2 (w'' orthogonal to V); when h2 is not small
+            // against w' that identity loses digits and w'' is formed and measured
+            // explicitly instead.
+            const int nv = j + 1;
+            double *vnext = V + (size_t)(j + 1) * n;
+            KCHK(launch_gs_dots(n, nv, V, w, pa, s));
+            KCHK(launch_gs_axpy_dots(n, nv, V, pa, hd, w, pq, s));
+            KCHK(launch_gs_reduce(n, nv + 1, pq, hd + 32, s));
+            HIPCHK(hipMemcpyAsync(hp, hd, 64 * sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hp[i] + hp[32 + i];
-            double hn = std::sqrt(hp[64]);
-            if (!std::isfinite(hn)) return SBM_ENONFINITE;
+            double h2sq = 0.0;
+            for (int i = 0; i <= j; ++i) h2sq += hp[32 + i] * hp[32 + i];
+            const double w1sq = hp[32 + nv];
+            if (!std::isfinite(w1sq) || !std::isfinite(h2sq)) return SBM_ENONFINITE;
+            double hn;
+            if (h2sq <= 0.5 * w1sq) {
+                hn = std::sqrt(w1sq - h2sq);
+                KCHK(launch_gs_axpy_scale(n, nv, V, hd + 32, hn > 0.0 ? 1.0 / hn : 1.0, w, vnext, s));
+            } else {
+                KCHK(launch_gs_axpy_dots(n, nv, V, pq, hd + 64, w, pa, s));
+                KCHK(launch_gs_reduce(n, nv + 1, pa, hd + 64, s));
+                HIPCHK(hipMemcpyAsync(hp + 64, hd + 64 + nv, sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                hn = std::sqrt(hp[64]);
+                if (!std::isfinite(hn)) return SBM_ENONFINITE;
+                KCHK(launch_scale(n, hd + 64 + nv, w, vnext, s));
+            }
             H[(size_t)(j + 1) * m + j] = hn;
             for (int i = 0; i < j; ++i) {
                 double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
@@ -796,7 +817,8 @@ int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, in
         KCHK(launch_multiaxpy(n, j, 1.0, hd + 96, Z, x, s));
         // true residual
         if ((rc = level_apply<double>(pb, lf, OP_RESID, x, w, b))) return rc;
-        KCHK(launch_multidot(n, 1, w, w, pb->red, hd + 64, s));
+        KCHK(launch_gs_dots(n, 0, nullptr, w, pa, s));
+        KCHK(launch_gs_reduce(n, 1, pa, hd + 64, s));
         HIPCHK(hipMemcpyAsync(hp, hd + 64, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         beta = std::sqrt(hp[0]);
