@@ -46,6 +46,7 @@ struct KRef {
     T gq[MAXN1];
     T g[2][MAXN1];
     T x[MAXN1];
+    T bw[MAXN1];            // barycentric weights 1 / prod_{b != a} (x_a - x_b) of the nodes x
     T sigF, sigG, alpha, scale, omega;
     int ext;
 };

@@ -77,51 +77,397 @@ __device__ __forceinline__ void decompose(int i, int k, int &m, int &j) {
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void lagrange_dev(const T *nodes, int n1, T x, T *v) {
-    for (int a = 0; a < n1; ++a) {
-        T num = 1, den = 1;
-        for (int b = 0; b < n1; ++b) {
-            if (b == a) continue;
-            num *= x - nodes[b];
-            den *= nodes[a] - nodes[b];
-        }
-        v[a] = num / den;
+// Lagrange basis of the nodes at x in barycentric form: v_a = bw_a prod_{b != a} (x - x_b)
+template <typename T, int N1>
+__device__ __forceinline__ void lagrange_dev(const T *nodes, const T *bw, T x, T *v) {
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+        T num = bw[a];
+#pragma unroll
+        for (int b = 0; b < N1; ++b)
+            if (b != a) num *= x - nodes[b];
+        v[a] = num;
     }
 }
 
 // --------------------------------------------------------------------------
-// Cell operator kernel.
+// Cell operator.
 //  OP_APPLY : out = A x
 //  OP_RESID : out = b - A x
 //  OP_SMOOTH: x (= out, in place) += omega * B_K (b - A x)_K on cells [cell0, cell0+ncells)
-template <int D, int P, typename T, int OP>
-__global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, const T *xin, T *out,
-                                                    const T *__restrict__ b, CellArgs<T> a, KRef<T> R) {
-    using S = Sh<D, P>;
-    constexpr int N1 = S::N1, NC = S::NC, NF = S::NF, CPB = S::CPB, NFACE = S::NFACE;
-    __shared__ T su[CPB][NC];
-    __shared__ T sa[CPB][NC];
-    __shared__ T sb[CPB][NC];
-    __shared__ T fa[CPB][NFACE][NF];
-    __shared__ T fb[CPB][NFACE][NF];
-    __shared__ T ga[CPB][NFACE][NF];
-    __shared__ T gb[CPB][NFACE][NF];
-    __shared__ int snb[CPB][NFACE];
-    __shared__ T sB[OP == OP_SMOOTH ? NC * NC : 1];  // shared interior-cell inverse
 
+// LDS of one block of NW waves (CPW cells per wave)
+template <int D, int P, typename T, int NW>
+struct CellLds {
+    static constexpr int NC = Sh<D, P>::NC, NF = Sh<D, P>::NF, NFACE = 2 * D, CPB = NW * Sh<D, P>::CPW;
+    T su[CPB][NC];
+    T sa[CPB][NC];
+    T sb[CPB][NC];
+    T fa[CPB][NFACE][NF];
+    T fb[CPB][NFACE][NF];
+    T ga[CPB][NFACE][NF];
+    T gb[CPB][NFACE][NF];
+    int snb[CPB][NFACE];
+};
+
+// One batch of cells [bstart, bend), at most NW * CPW of them: wave w takes the
+// cells bstart + w * CPW + (0 .. CPW-1), one thread per DoF.  R and sB (the
+// transposed interior-cell inverse, OP_SMOOTH) are block-shared LDS copies;
+// with first (uniform over the block) a block barrier precedes their first
+// read, so that their staging overlaps the batch's cell-data loads.
+//
+// Every global load is issued as early as its address is known, so that a
+// batch costs three dependent memory round trips (cell data; neighbour traces,
+// shift vectors and the boundary-cell inverse; the store) rather than one per
+// stage: small levels are bound by this latency.
+template <int D, int P, typename T, int OP, int NW>
+__device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB, bool first, int bstart, int bend,
+                                           const T *xin, T *out, const T *__restrict__ b, const CellArgs<T> &a,
+                                           const KRef<T> &R) {
+    using S = Sh<D, P>;
+    constexpr int N1 = S::N1, NC = S::NC, NF = S::NF, NFACE = S::NFACE;
+    auto &su = L.su;
+    auto &sa = L.sa;
+    auto &sb = L.sb;
+    auto &fa = L.fa;
+    auto &fb = L.fb;
+    auto &ga = L.ga;
+    auto &gb = L.gb;
+    auto &snb = L.snb;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const bool slot = lane < S::CPW * NC;
     const int lc = slot ? wave * S::CPW + lane / NC : 0;
     const int i = slot ? lane % NC : 0;
-    // Every global load is issued as early as its address is known, so that a
-    // batch costs three dependent memory round trips (cell data; neighbour
-    // traces, shift vectors and the boundary-cell inverse; the store) rather
-    // than one per stage: small levels are bound by this latency.
-    if (OP == OP_SMOOTH) {
-        // staged here, first read after a block barrier in the output stage
-        for (int t = threadIdx.x; t < NC * NC; t += blockDim.x) sB[t] = a.Bint_t[t];
+    const int cell = bstart + lc;
+    const bool live = slot && cell < bend;
+    wave_sync();  // the previous batch is done with this wave's LDS slices
+
+    T bval = 0;
+    int bi = -1;
+    if (live) {
+        su[lc][i] = xin[(size_t)cell * NC + i];
+        if (i < NFACE) snb[lc][i] = a.nbr[(size_t)cell * NFACE + i];
+        if (OP != OP_APPLY) bval = b[(size_t)cell * NC + i];
+        if (OP == OP_SMOOTH) bi = a.bnd_of[cell];
     }
+    wave_sync();
+    if (first) __syncthreads();   // R and sB staged
+
+    // Face items (face f, tangential index j) handled by this thread: the
+    // neighbour's nodes on the line through the face point (interior
+    // faces) or the shift vector at the face Gauss point (surrogate
+    // faces).  Loaded here, consumed after the volume stage.
+    constexpr int ITEMS = (NFACE * NF + NC - 1) / NC;
+    constexpr bool PRE_B = NC <= 9;   // boundary-cell inverse column kept in registers
+    T raw[ITEMS][N1];
+    T dqr[ITEMS][D];
+    T bcol[PRE_B ? NC : 1];
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) {
+            int it = i + q * NC;
+            if (it < NFACE * NF) {
+                int f = it / NF, j = it % NF, k = f >> 1;
+                int nb = snb[lc][f];
+                if (nb >= 0) {
+                    const T *un = xin + (size_t)nb * NC;
+#pragma unroll
+                    for (int m = 0; m < N1; ++m) raw[q][m] = un[compose<D, P>(k, m, j)];
+                } else {
+                    const T *dq = a.shift + ((size_t)(-nb - 1) * NF + j) * D;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) dqr[q][c] = dq[c];
+                }
+            }
+        }
+        if (OP == OP_SMOOTH && PRE_B && bi >= 0) {
+            const T *Bt = a.Bbnd_t + (size_t)bi * NC * NC;
+#pragma unroll
+            for (int j = 0; j < (PRE_B ? NC : 1); ++j) bcol[j] = Bt[(size_t)j * NC + i];
+        }
+    }
+
+    // ---------------- volume + unshifted self terms (sum factorisation)
+    T y = 0;
+    int c0 = i % N1, c1 = (i / N1) % N1, c2 = D == 3 ? i / (N1 * N1) : 0;
+    int vx = 0, vy = 0, vz = 0;
+    if (live) {
+        vx = (snb[lc][0] < 0) + 2 * (snb[lc][1] < 0);
+        vy = (snb[lc][2] < 0) + 2 * (snb[lc][3] < 0);
+        if (D == 3) vz = (snb[lc][4] < 0) + 2 * (snb[lc][5] < 0);
+        T am = 0, bt = 0;
+        int base = i - c0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            T u = su[lc][base + m];
+            am += R.M[c0][m] * u;
+            bt += R.Tv[vx][c0][m] * u;
+        }
+        sa[lc][i] = am;
+        sb[lc][i] = bt;
+    }
+    wave_sync();
+    if (D == 2) {
+        if (live) {
+#pragma unroll
+            for (int m = 0; m < N1; ++m) y += R.M[c1][m] * sb[lc][c0 + N1 * m] + R.Tv[vy][c1][m] * sa[lc][c0 + N1 * m];
+        }
+    } else {
+        T aM = 0, aT = 0, bM = 0;
+        if (live) {
+            int base = i - N1 * c1;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) {
+                T av = sa[lc][base + N1 * m], bv = sb[lc][base + N1 * m];
+                aM += R.M[c1][m] * av;
+                aT += R.Tv[vy][c1][m] * av;
+                bM += R.M[c1][m] * bv;
+            }
+        }
+        wave_sync();
+        if (live) {
+            sa[lc][i] = aM;
+            sb[lc][i] = aT + bM;
+        }
+        wave_sync();
+        if (live) {
+            int base = i - N1 * N1 * c2;
+#pragma unroll
+            for (int m = 0; m < N1; ++m)
+                y += R.M[c2][m] * sb[lc][base + N1 * N1 * m] + R.Tv[vz][c2][m] * sa[lc][base + N1 * N1 * m];
+        }
+    }
+
+    // ---------------- interior-face couplings: neighbour trace and normal derivative
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) {
+            int it = i + q * NC;
+            if (it >= NFACE * NF) break;
+            int f = it / NF, j = it % NF, s = f & 1;
+            int nb = snb[lc][f];
+            T va = 0, vb = 0;
+            if (nb >= 0) {
+                const T *gN = R.g[s == 1 ? 0 : 1];
+                T t = s == 1 ? raw[q][0] : raw[q][P];
+                T dn = 0;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) dn += gN[m] * raw[q][m];
+                T sg = s == 1 ? T(1) : T(-1);
+                va = T(-0.5) * sg * dn - R.sigF * t;
+                vb = T(0.5) * t;
+            }
+            fa[lc][f][j] = va;
+            fb[lc][f][j] = vb;
+        }
+    }
+    wave_sync();
+    // tangential mass along the first tangential direction
+    if (live) {
+        for (int it = i; it < NFACE * NF; it += NC) {
+            int f = it / NF, j = it % NF;
+            int j1 = j % N1, rest = j - j1;
+            T va = 0, vb = 0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) {
+                va += R.M[j1][m] * fa[lc][f][rest + m];
+                vb += R.M[j1][m] * fb[lc][f][rest + m];
+            }
+            ga[lc][f][j] = va;
+            gb[lc][f][j] = vb;
+        }
+    }
+    wave_sync();
+    if (D == 3) {
+        if (live) {
+            for (int it = i; it < NFACE * NF; it += NC) {
+                int f = it / NF, j = it % NF;
+                int j1 = j % N1, j2 = j / N1;
+                T va = 0, vb = 0;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) {
+                    va += R.M[j2][m] * ga[lc][f][j1 + N1 * m];
+                    vb += R.M[j2][m] * gb[lc][f][j1 + N1 * m];
+                }
+                fa[lc][f][j] = va;
+                fb[lc][f][j] = vb;
+            }
+        }
+        wave_sync();
+    }
+    if (live) {
+#pragma unroll
+        for (int f = 0; f < NFACE; ++f) {
+            if (snb[lc][f] < 0) continue;
+            int k = f >> 1, s = f & 1, m, j;
+            decompose<D, P>(i, k, m, j);
+            T ev = (m == (s ? P : 0)) ? T(1) : T(0);
+            T sg = s == 1 ? T(1) : T(-1);
+            T F1 = D == 3 ? fa[lc][f][j] : ga[lc][f][j];
+            T F2 = D == 3 ? fb[lc][f][j] : gb[lc][f][j];
+            y += ev * F1 + sg * R.g[s][m] * F2;
+        }
+    }
+    wave_sync();
+
+    // ---------------- shift part of the Nitsche terms on surrogate faces
+    bool bnd = false;
+    if (live) {
+#pragma unroll
+        for (int f = 0; f < NFACE; ++f) bnd |= snb[lc][f] < 0;
+    }
+    if (live && bnd) {
+#pragma unroll
+        for (int qi = 0; qi < ITEMS; ++qi) {
+            const int it = i + qi * NC;
+            if (it >= NFACE * NF) break;
+            int f = it / NF, q = it % NF, k = f >> 1, s = f & 1;
+            int nb = snb[lc][f];
+            T zeta = 0;
+            if (nb < 0) {
+                const T *dq = dqr[qi];
+                int q1 = q % N1, q2 = D == 3 ? q / N1 : 0;
+                T wq = R.w[q1] * (D == 3 ? R.w[q2] : T(1));
+                const int layer = s ? P : 0;
+                T E = 0;
+                // boundary cells only: loops stay rolled to keep register pressure
+                // of the whole kernel low
+                if (R.ext == 0) {
+                    // gradient of u at the face Gauss point
+                    T dk = 0, dt1 = 0, dt2 = 0;
+#pragma unroll 1
+                    for (int j = 0; j < NF; ++j) {
+                        int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
+                        T s1 = R.S[q1][j1], s2 = D == 3 ? R.S[q2][j2] : T(1);
+                        T d1 = R.Sd[q1][j1], d2 = D == 3 ? R.Sd[q2][j2] : T(0);
+                        T nd = 0;
+#pragma unroll
+                        for (int m = 0; m < N1; ++m) nd += R.g[s][m] * su[lc][compose<D, P>(k, m, j)];
+                        T ul = su[lc][compose<D, P>(k, layer, j)];
+                        dk += s1 * s2 * nd;
+                        dt1 += d1 * s2 * ul;
+                        if (D == 3) dt2 += s1 * d2 * ul;
+                    }
+                    int t1 = k == 0 ? 1 : 0;
+                    int t2 = k == 2 ? 1 : 2;
+                    // components picked with selects: dq lives in registers
+                    const T dk_k = k == 0 ? dq[0] : (k == 1 ? dq[1] : dq[D - 1]);
+                    const T dk_t1 = t1 == 0 ? dq[0] : dq[1];
+                    E = dk_k * dk + dk_t1 * dt1;
+                    if (D == 3) E += (t2 == 1 ? dq[1] : dq[D - 1]) * dt2;
+                } else {
+                    // cell polynomial at the shifted point minus its value at the face point
+                    T lv[3][N1];
+                    const int t1 = k == 0 ? 1 : 0;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        T xc = c == k ? T(s) : (c == t1 ? R.gq[q1] : R.gq[q2]);
+                        lagrange_dev<T, N1>(R.x, R.bw, xc + dq[c], lv[c]);
+                    }
+                    T acc = 0, face = 0;
+#pragma unroll 1
+                    for (int jj = 0; jj < NC; ++jj) {
+                        int a0 = jj % N1, a1 = (jj / N1) % N1, a2 = D == 3 ? jj / (N1 * N1) : 0;
+                        T pv = lv[0][a0] * lv[1][a1];
+                        if (D == 3) pv *= lv[2][a2];
+                        acc += pv * su[lc][jj];
+                    }
+#pragma unroll 1
+                    for (int j = 0; j < NF; ++j) {
+                        int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
+                        T sv = R.S[q1][j1] * (D == 3 ? R.S[q2][j2] : T(1));
+                        face += sv * su[lc][compose<D, P>(k, layer, j)];
+                    }
+                    E = acc - face;
+                }
+                zeta = wq * E;
+            }
+            fa[lc][f][q] = zeta;
+        }
+    }
+    wave_sync();
+    if (live && bnd) {
+#pragma unroll
+        for (int f = 0; f < NFACE; ++f) {
+            if (snb[lc][f] >= 0) continue;
+            int k = f >> 1, s = f & 1, m, j;
+            decompose<D, P>(i, k, m, j);
+            T sg = s == 1 ? T(1) : T(-1);
+            T ev = (m == (s ? P : 0)) ? T(1) : T(0);
+            T coef = -R.alpha * sg * R.g[s][m] + R.sigG * ev;
+            int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
+            T acc = 0;
+#pragma unroll 1
+            for (int q = 0; q < NF; ++q) {
+                int q1 = q % N1, q2 = D == 3 ? q / N1 : 0;
+                T sv = R.S[q1][j1] * (D == 3 ? R.S[q2][j2] : T(1));
+                acc += fa[lc][f][q] * sv;
+            }
+            y += coef * acc;
+        }
+    }
+
+    // ---------------- output
+    y *= R.scale;
+    if (OP == OP_APPLY) {
+        if (live) out[(size_t)cell * NC + i] = y;
+    } else if (OP == OP_RESID) {
+        if (live) out[(size_t)cell * NC + i] = bval - y;
+    } else {
+        wave_sync();
+        if (live) sa[lc][i] = bval - y;
+        wave_sync();
+        if (live) {
+            T corr = 0;
+            if (bi < 0) {
+#pragma unroll 4
+                for (int j = 0; j < NC; ++j) corr += sB[j * NC + i] * sa[lc][j];
+            } else if (PRE_B) {
+#pragma unroll
+                for (int j = 0; j < (PRE_B ? NC : 1); ++j) corr += bcol[j] * sa[lc][j];
+            } else {
+                const T *Bt = a.Bbnd_t + (size_t)bi * NC * NC;
+#pragma unroll 2
+                for (int j = 0; j < NC; ++j) corr += Bt[(size_t)j * NC + i] * sa[lc][j];
+            }
+            if (a.lw != nullptr && bi >= 0) {
+                const T *U = a.lU + (size_t)bi * NC * 4;
+                const T *V = a.lV + (size_t)bi * NC * 4;
+                T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+#pragma unroll 1
+                for (int j = 0; j < NC; ++j) {
+                    T r = sa[lc][j];
+                    v0 += V[j * 4 + 0] * r;
+                    v1 += V[j * 4 + 1] * r;
+                    v2 += V[j * 4 + 2] * r;
+                    v3 += V[j * 4 + 3] * r;
+                }
+                corr += U[i * 4 + 0] * v0 + U[i * 4 + 1] * v1 + U[i * 4 + 2] * v2 + U[i * 4 + 3] * v3;
+                corr *= a.lw[bi];
+            }
+            out[(size_t)cell * NC + i] = su[lc][i] + R.omega * corr;
+        }
+    }
+}
+
+template <int D, int P, typename T, int OP>
+__global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, const T *xin, T *out,
+                                                    const T *__restrict__ b, CellArgs<T> a, KRef<T> Rarg) {
+    using S = Sh<D, P>;
+    constexpr int NC = S::NC, CPB = S::CPB;
+    __shared__ CellLds<D, P, T, S::WAVES> L;
+    __shared__ T sB[OP == OP_SMOOTH ? NC * NC : 1];  // shared interior-cell inverse
+    __shared__ KRef<T> sR;
+    // The reference data are indexed per lane; read from the kernel arguments
+    // every access would be a memory round trip on the critical path.
+    {
+        static_assert(sizeof(KRef<T>) % 4 == 0, "KRef is copied as 32-bit words");
+        const unsigned *src = reinterpret_cast<const unsigned *>(&Rarg);
+        unsigned *dst = reinterpret_cast<unsigned *>(&sR);
+        for (int t = threadIdx.x; t < (int)(sizeof(KRef<T>) / 4); t += blockDim.x) dst[t] = src[t];
+    }
+    if (OP == OP_SMOOTH)
+        for (int t = threadIdx.x; t < NC * NC; t += blockDim.x) sB[t] = a.Bint_t[t];
     // Each block owns a contiguous chunk of cell batches (one batch per block
     // for the apply, several for the smoother so that sB is staged once per
     // chunk); the remap gives every XCD a contiguous range of cells.
@@ -140,317 +486,8 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
             bstart = cell0 + bb * CPB;
             bend = cell0 + ncells;
         }
-        const int cell = bstart + lc;
-        const bool live = slot && cell < bend;
-        wave_sync();  // the previous batch is done with this wave's LDS slices
-
-        T bval = 0;
-        int bi = -1;
-        if (live) {
-            su[lc][i] = xin[(size_t)cell * NC + i];
-            if (i < NFACE) snb[lc][i] = a.nbr[(size_t)cell * NFACE + i];
-            if (OP != OP_APPLY) bval = b[(size_t)cell * NC + i];
-            if (OP == OP_SMOOTH) bi = a.bnd_of[cell];
-        }
-        wave_sync();
-
-        // Face items (face f, tangential index j) handled by this thread: the
-        // neighbour's nodes on the line through the face point (interior
-        // faces) or the shift vector at the face Gauss point (surrogate
-        // faces).  Loaded here, consumed after the volume stage.
-        constexpr int ITEMS = (NFACE * NF + NC - 1) / NC;
-        constexpr bool PRE_B = NC <= 9;   // boundary-cell inverse column kept in registers
-        T raw[ITEMS][N1];
-        T dqr[ITEMS][D];
-        T bcol[PRE_B ? NC : 1];
-        if (live) {
-#pragma unroll
-            for (int q = 0; q < ITEMS; ++q) {
-                int it = i + q * NC;
-                if (it < NFACE * NF) {
-                    int f = it / NF, j = it % NF, k = f >> 1;
-                    int nb = snb[lc][f];
-                    if (nb >= 0) {
-                        const T *un = xin + (size_t)nb * NC;
-#pragma unroll
-                        for (int m = 0; m < N1; ++m) raw[q][m] = un[compose<D, P>(k, m, j)];
-                    } else {
-                        const T *dq = a.shift + ((size_t)(-nb - 1) * NF + j) * D;
-#pragma unroll
-                        for (int c = 0; c < D; ++c) dqr[q][c] = dq[c];
-                    }
-                }
-            }
-            if (OP == OP_SMOOTH && PRE_B && bi >= 0) {
-                const T *Bt = a.Bbnd_t + (size_t)bi * NC * NC;
-#pragma unroll
-                for (int j = 0; j < (PRE_B ? NC : 1); ++j) bcol[j] = Bt[(size_t)j * NC + i];
-            }
-        }
-
-        // ---------------- volume + unshifted self terms (sum factorisation)
-        T y = 0;
-        int c0 = i % N1, c1 = (i / N1) % N1, c2 = D == 3 ? i / (N1 * N1) : 0;
-        int vx = 0, vy = 0, vz = 0;
-        if (live) {
-            vx = (snb[lc][0] < 0) + 2 * (snb[lc][1] < 0);
-            vy = (snb[lc][2] < 0) + 2 * (snb[lc][3] < 0);
-            if (D == 3) vz = (snb[lc][4] < 0) + 2 * (snb[lc][5] < 0);
-            T am = 0, bt = 0;
-            int base = i - c0;
-#pragma unroll
-            for (int m = 0; m < N1; ++m) {
-                T u = su[lc][base + m];
-                am += R.M[c0][m] * u;
-                bt += R.Tv[vx][c0][m] * u;
-            }
-            sa[lc][i] = am;
-            sb[lc][i] = bt;
-        }
-        wave_sync();
-        if (D == 2) {
-            if (live) {
-#pragma unroll
-                for (int m = 0; m < N1; ++m) y += R.M[c1][m] * sb[lc][c0 + N1 * m] + R.Tv[vy][c1][m] * sa[lc][c0 + N1 * m];
-            }
-        } else {
-            T aM = 0, aT = 0, bM = 0;
-            if (live) {
-                int base = i - N1 * c1;
-#pragma unroll
-                for (int m = 0; m < N1; ++m) {
-                    T av = sa[lc][base + N1 * m], bv = sb[lc][base + N1 * m];
-                    aM += R.M[c1][m] * av;
-                    aT += R.Tv[vy][c1][m] * av;
-                    bM += R.M[c1][m] * bv;
-                }
-            }
-            wave_sync();
-            if (live) {
-                sa[lc][i] = aM;
-                sb[lc][i] = aT + bM;
-            }
-            wave_sync();
-            if (live) {
-                int base = i - N1 * N1 * c2;
-#pragma unroll
-                for (int m = 0; m < N1; ++m)
-                    y += R.M[c2][m] * sb[lc][base + N1 * N1 * m] + R.Tv[vz][c2][m] * sa[lc][base + N1 * N1 * m];
-            }
-        }
-
-        // ---------------- interior-face couplings: neighbour trace and normal derivative
-        if (live) {
-#pragma unroll
-            for (int q = 0; q < ITEMS; ++q) {
-                int it = i + q * NC;
-                if (it >= NFACE * NF) break;
-                int f = it / NF, j = it % NF, s = f & 1;
-                int nb = snb[lc][f];
-                T va = 0, vb = 0;
-                if (nb >= 0) {
-                    const T *gN = R.g[s == 1 ? 0 : 1];
-                    T t = s == 1 ? raw[q][0] : raw[q][P];
-                    T dn = 0;
-#pragma unroll
-                    for (int m = 0; m < N1; ++m) dn += gN[m] * raw[q][m];
-                    T sg = s == 1 ? T(1) : T(-1);
-                    va = T(-0.5) * sg * dn - R.sigF * t;
-                    vb = T(0.5) * t;
-                }
-                fa[lc][f][j] = va;
-                fb[lc][f][j] = vb;
-            }
-        }
-        wave_sync();
-        // tangential mass along the first tangential direction
-        if (live) {
-            for (int it = i; it < NFACE * NF; it += NC) {
-                int f = it / NF, j = it % NF;
-                int j1 = j % N1, rest = j - j1;
-                T va = 0, vb = 0;
-#pragma unroll
-                for (int m = 0; m < N1; ++m) {
-                    va += R.M[j1][m] * fa[lc][f][rest + m];
-                    vb += R.M[j1][m] * fb[lc][f][rest + m];
-                }
-                ga[lc][f][j] = va;
-                gb[lc][f][j] = vb;
-            }
-        }
-        wave_sync();
-        if (D == 3) {
-            if (live) {
-                for (int it = i; it < NFACE * NF; it += NC) {
-                    int f = it / NF, j = it % NF;
-                    int j1 = j % N1, j2 = j / N1;
-                    T va = 0, vb = 0;
-#pragma unroll
-                    for (int m = 0; m < N1; ++m) {
-                        va += R.M[j2][m] * ga[lc][f][j1 + N1 * m];
-                        vb += R.M[j2][m] * gb[lc][f][j1 + N1 * m];
-                    }
-                    fa[lc][f][j] = va;
-                    fb[lc][f][j] = vb;
-                }
-            }
-            wave_sync();
-        }
-        if (live) {
-#pragma unroll
-            for (int f = 0; f < NFACE; ++f) {
-                if (snb[lc][f] < 0) continue;
-                int k = f >> 1, s = f & 1, m, j;
-                decompose<D, P>(i, k, m, j);
-                T ev = (m == (s ? P : 0)) ? T(1) : T(0);
-                T sg = s == 1 ? T(1) : T(-1);
-                T F1 = D == 3 ? fa[lc][f][j] : ga[lc][f][j];
-                T F2 = D == 3 ? fb[lc][f][j] : gb[lc][f][j];
-                y += ev * F1 + sg * R.g[s][m] * F2;
-            }
-        }
-        wave_sync();
-
-        // ---------------- shift part of the Nitsche terms on surrogate faces
-        bool bnd = false;
-        if (live) {
-#pragma unroll
-            for (int f = 0; f < NFACE; ++f) bnd |= snb[lc][f] < 0;
-        }
-        if (live && bnd) {
-#pragma unroll
-            for (int qi = 0; qi < ITEMS; ++qi) {
-                const int it = i + qi * NC;
-                if (it >= NFACE * NF) break;
-                int f = it / NF, q = it % NF, k = f >> 1, s = f & 1;
-                int nb = snb[lc][f];
-                T zeta = 0;
-                if (nb < 0) {
-                    const T *dq = dqr[qi];
-                    int q1 = q % N1, q2 = D == 3 ? q / N1 : 0;
-                    T wq = R.w[q1] * (D == 3 ? R.w[q2] : T(1));
-                    const int layer = s ? P : 0;
-                    T E = 0;
-                    // boundary cells only: loops stay rolled to keep register pressure
-                    // of the whole kernel low
-                    if (R.ext == 0) {
-                        // gradient of u at the face Gauss point
-                        T dk = 0, dt1 = 0, dt2 = 0;
-#pragma unroll 1
-                        for (int j = 0; j < NF; ++j) {
-                            int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
-                            T s1 = R.S[q1][j1], s2 = D == 3 ? R.S[q2][j2] : T(1);
-                            T d1 = R.Sd[q1][j1], d2 = D == 3 ? R.Sd[q2][j2] : T(0);
-                            T nd = 0;
-#pragma unroll
-                            for (int m = 0; m < N1; ++m) nd += R.g[s][m] * su[lc][compose<D, P>(k, m, j)];
-                            T ul = su[lc][compose<D, P>(k, layer, j)];
-                            dk += s1 * s2 * nd;
-                            dt1 += d1 * s2 * ul;
-                            if (D == 3) dt2 += s1 * d2 * ul;
-                        }
-                        int t1 = k == 0 ? 1 : 0;
-                        int t2 = k == 2 ? 1 : 2;
-                        // components picked with selects: dq lives in registers
-                        const T dk_k = k == 0 ? dq[0] : (k == 1 ? dq[1] : dq[D - 1]);
-                        const T dk_t1 = t1 == 0 ? dq[0] : dq[1];
-                        E = dk_k * dk + dk_t1 * dt1;
-                        if (D == 3) E += (t2 == 1 ? dq[1] : dq[D - 1]) * dt2;
-                    } else {
-                        // cell polynomial at the shifted point minus its value at the face point
-                        T lv[3][N1];
-                        const int t1 = k == 0 ? 1 : 0;
-#pragma unroll
-                        for (int c = 0; c < D; ++c) {
-                            T xc = c == k ? T(s) : (c == t1 ? R.gq[q1] : R.gq[q2]);
-                            lagrange_dev<T>(R.x, N1, xc + dq[c], lv[c]);
-                        }
-                        T acc = 0, face = 0;
-#pragma unroll 1
-                        for (int jj = 0; jj < NC; ++jj) {
-                            int a0 = jj % N1, a1 = (jj / N1) % N1, a2 = D == 3 ? jj / (N1 * N1) : 0;
-                            T pv = lv[0][a0] * lv[1][a1];
-                            if (D == 3) pv *= lv[2][a2];
-                            acc += pv * su[lc][jj];
-                        }
-#pragma unroll 1
-                        for (int j = 0; j < NF; ++j) {
-                            int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
-                            T sv = R.S[q1][j1] * (D == 3 ? R.S[q2][j2] : T(1));
-                            face += sv * su[lc][compose<D, P>(k, layer, j)];
-                        }
-                        E = acc - face;
-                    }
-                    zeta = wq * E;
-                }
-                fa[lc][f][q] = zeta;
-            }
-        }
-        wave_sync();
-        if (live && bnd) {
-#pragma unroll
-            for (int f = 0; f < NFACE; ++f) {
-                if (snb[lc][f] >= 0) continue;
-                int k = f >> 1, s = f & 1, m, j;
-                decompose<D, P>(i, k, m, j);
-                T sg = s == 1 ? T(1) : T(-1);
-                T ev = (m == (s ? P : 0)) ? T(1) : T(0);
-                T coef = -R.alpha * sg * R.g[s][m] + R.sigG * ev;
-                int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
-                T acc = 0;
-#pragma unroll 1
-                for (int q = 0; q < NF; ++q) {
-                    int q1 = q % N1, q2 = D == 3 ? q / N1 : 0;
-                    T sv = R.S[q1][j1] * (D == 3 ? R.S[q2][j2] : T(1));
-                    acc += fa[lc][f][q] * sv;
-                }
-                y += coef * acc;
-            }
-        }
-
-        // ---------------- output
-        y *= R.scale;
-        if (OP == OP_APPLY) {
-            if (live) out[(size_t)cell * NC + i] = y;
-        } else if (OP == OP_RESID) {
-            if (live) out[(size_t)cell * NC + i] = bval - y;
-        } else {
-            wave_sync();
-            if (live) sa[lc][i] = bval - y;
-            if (bb == bb0) __syncthreads();   // sB staged (block-uniform branch)
-            wave_sync();
-            if (live) {
-                T corr = 0;
-                if (bi < 0) {
-#pragma unroll 4
-                    for (int j = 0; j < NC; ++j) corr += sB[j * NC + i] * sa[lc][j];
-                } else if (PRE_B) {
-#pragma unroll
-                    for (int j = 0; j < (PRE_B ? NC : 1); ++j) corr += bcol[j] * sa[lc][j];
-                } else {
-                    const T *Bt = a.Bbnd_t + (size_t)bi * NC * NC;
-#pragma unroll 2
-                    for (int j = 0; j < NC; ++j) corr += Bt[(size_t)j * NC + i] * sa[lc][j];
-                }
-                if (a.lw != nullptr && bi >= 0) {
-                    const T *U = a.lU + (size_t)bi * NC * 4;
-                    const T *V = a.lV + (size_t)bi * NC * 4;
-                    T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-#pragma unroll 1
-                    for (int j = 0; j < NC; ++j) {
-                        T r = sa[lc][j];
-                        v0 += V[j * 4 + 0] * r;
-                        v1 += V[j * 4 + 1] * r;
-                        v2 += V[j * 4 + 2] * r;
-                        v3 += V[j * 4 + 3] * r;
-                    }
-                    corr += U[i * 4 + 0] * v0 + U[i * 4 + 1] * v1 + U[i * 4 + 2] * v2 + U[i * 4 + 3] * v3;
-                    corr *= a.lw[bi];
-                }
-                out[(size_t)cell * NC + i] = su[lc][i] + R.omega * corr;
-            }
-        }
-    }  // batch loop
+        cell_batch<D, P, T, OP, S::WAVES>(L, sB, bb == bb0, bstart, bend, xin, out, b, a, sR);
+    }
 }
 
 template <int D, int P, typename T>
@@ -493,11 +530,9 @@ template int launch_cellop<float>(int, int, int, int, int, const float *, float 
 // learned correction where present) and colour-1 cells z_K = 0.  One thread
 // per DoF; replaces clearing z plus a full colour-0 update.
 template <int D, int P, typename T>
-__global__ __launch_bounds__(256) void smooth_zero_kernel(int n_act, int split, const T *__restrict__ b,
-                                                          T *__restrict__ z, CellArgs<T> a, T omega) {
+__device__ __forceinline__ void smooth_zero_dof(long long t, int split, const T *__restrict__ b, T *__restrict__ z,
+                                                const CellArgs<T> &a, T omega) {
     constexpr int NC = Sh<D, P>::NC;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)n_act * NC) return;
     const int cell = (int)(t / NC), i = (int)(t % NC);
     T out = 0;
     if (cell < split) {
@@ -525,6 +560,14 @@ __global__ __launch_bounds__(256) void smooth_zero_kernel(int n_act, int split, 
         out = T(0) + omega * corr;
     }
     z[t] = out;
+}
+
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void smooth_zero_kernel(int n_act, int split, const T *__restrict__ b,
+                                                          T *__restrict__ z, CellArgs<T> a, T omega) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)n_act * Sh<D, P>::NC) return;
+    smooth_zero_dof<D, P, T>(t, split, b, z, a, omega);
 }
 
 template <int D, int P, typename T>
@@ -559,22 +602,24 @@ template int launch_smooth_zero<float>(int, int, int, int, const float *, float 
 // Transfers (Sec. 3.2): prolongation = embedding of the coarse cell polynomial
 // into the fine cell(s), restriction = its transpose; inactive parents give
 // zero and restriction into inactive coarse cells is dropped.
+template <typename T>
+using P1Table = T[2][MAXN1][MAXN1];
+
+// fine DoF gid (cell K, node i) += coarse parent polynomial at that node
 template <int D, typename T>
-__global__ __launch_bounds__(256) void prolong_kernel(int n_fine, int n1f, int n1c, const int *__restrict__ parent,
-                                                      const int *__restrict__ childpos, const T *__restrict__ zc,
-                                                      T *__restrict__ zf, TransferArgs<T> tr) {
+__device__ __forceinline__ void prolong_dof(long long gid, int n1f, int n1c, const int *__restrict__ parent,
+                                            const int *__restrict__ childpos, const T *__restrict__ zc,
+                                            T *__restrict__ zf, const P1Table<T> &P1t) {
     int ncf = D == 2 ? n1f * n1f : n1f * n1f * n1f;
     int ncc = D == 2 ? n1c * n1c : n1c * n1c * n1c;
-    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (long long)n_fine * ncf) return;
     int K = (int)(gid / ncf), i = (int)(gid % ncf);
     int pc = parent[K];
     if (pc < 0) return;
     int o = childpos[K];
     int i0 = i % n1f, i1 = (i / n1f) % n1f, i2 = D == 3 ? i / (n1f * n1f) : 0;
-    const T *P0 = tr.P1[o & 1][i0];
-    const T *P1 = tr.P1[(o >> 1) & 1][i1];
-    const T *P2 = tr.P1[(o >> 2) & 1][i2];
+    const T *P0 = P1t[o & 1][i0];
+    const T *P1 = P1t[(o >> 1) & 1][i1];
+    const T *P2 = P1t[(o >> 2) & 1][i2];
     const T *src = zc + (size_t)pc * ncc;
     T acc = 0;
     for (int j = 0; j < ncc; ++j) {
@@ -586,14 +631,13 @@ __global__ __launch_bounds__(256) void prolong_kernel(int n_fine, int n1f, int n
     zf[(size_t)K * ncf + i] += acc;
 }
 
+// coarse DoF gid (cell Kc, node j) = sum over the children of the transposed embedding
 template <int D, typename T>
-__global__ __launch_bounds__(256) void restrict_kernel(int n_coarse, int n1f, int n1c, int nch,
-                                                       const int *__restrict__ children, const T *__restrict__ rf,
-                                                       T *__restrict__ bc, TransferArgs<T> tr) {
+__device__ __forceinline__ void restrict_dof(long long gid, int n1f, int n1c, int nch,
+                                             const int *__restrict__ children, const T *__restrict__ rf,
+                                             T *__restrict__ bc, const P1Table<T> &P1t) {
     int ncf = D == 2 ? n1f * n1f : n1f * n1f * n1f;
     int ncc = D == 2 ? n1c * n1c : n1c * n1c * n1c;
-    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (long long)n_coarse * ncc) return;
     int Kc = (int)(gid / ncc), j = (int)(gid % ncc);
     int j0 = j % n1c, j1 = (j / n1c) % n1c, j2 = D == 3 ? j / (n1c * n1c) : 0;
     T acc = 0;
@@ -603,12 +647,32 @@ __global__ __launch_bounds__(256) void restrict_kernel(int n_coarse, int n1f, in
         const T *src = rf + (size_t)K * ncf;
         for (int i = 0; i < ncf; ++i) {
             int i0 = i % n1f, i1 = (i / n1f) % n1f, i2 = D == 3 ? i / (n1f * n1f) : 0;
-            T w = tr.P1[o & 1][i0][j0] * tr.P1[(o >> 1) & 1][i1][j1];
-            if (D == 3) w *= tr.P1[(o >> 2) & 1][i2][j2];
+            T w = P1t[o & 1][i0][j0] * P1t[(o >> 1) & 1][i1][j1];
+            if (D == 3) w *= P1t[(o >> 2) & 1][i2][j2];
             acc += w * src[i];
         }
     }
     bc[(size_t)Kc * ncc + j] = acc;
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void prolong_kernel(int n_fine, int n1f, int n1c, const int *__restrict__ parent,
+                                                      const int *__restrict__ childpos, const T *__restrict__ zc,
+                                                      T *__restrict__ zf, TransferArgs<T> tr) {
+    int ncf = D == 2 ? n1f * n1f : n1f * n1f * n1f;
+    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long long)n_fine * ncf) return;
+    prolong_dof<D, T>(gid, n1f, n1c, parent, childpos, zc, zf, tr.P1);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void restrict_kernel(int n_coarse, int n1f, int n1c, int nch,
+                                                       const int *__restrict__ children, const T *__restrict__ rf,
+                                                       T *__restrict__ bc, TransferArgs<T> tr) {
+    int ncc = D == 2 ? n1c * n1c : n1c * n1c * n1c;
+    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long long)n_coarse * ncc) return;
+    restrict_dof<D, T>(gid, n1f, n1c, nch, children, rf, bc, tr.P1);
 }
 
 template <typename T>
@@ -649,16 +713,34 @@ template int launch_restrict<float>(int, int, int, int, int, const int *, const 
 // Coarsest level: z = A0^{-1} b with the dense inverse, accumulated in the
 // matrix type TA (the FP32 cycle passes FP32 vectors and the FP64 inverse).
 template <typename TA, typename TX>
+__device__ __forceinline__ void gemv_row(int n, int row, const TA *__restrict__ A, const TX *__restrict__ x,
+                                         TX *__restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const TA *a = A + (size_t)row * n;
+    TA acc = 0;
+    // lane sum over j = lane, lane + 64, ... in that order; four loads in flight
+    for (int j0 = lane; j0 < n; j0 += 256) {
+        TA av[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = j0 + 64 * u;
+            av[u] = j < n ? a[j] : TA(0);
+            xv[u] = j < n ? (TA)x[j] : TA(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += av[u] * xv[u];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) y[row] = (TX)acc;
+}
+
+template <typename TA, typename TX>
 __global__ __launch_bounds__(256) void dense_gemv_kernel(int n, const TA *__restrict__ A, const TX *__restrict__ x,
                                                          TX *__restrict__ y) {
     // one wave per row: the lanes stride over the row (coalesced), then reduce
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n) return;
-    const TA *a = A + (size_t)row * n;
-    TA acc = 0;
-    for (int j = lane; j < n; j += 64) acc += a[j] * (TA)x[j];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (lane == 0) y[row] = (TX)acc;
+    gemv_row(n, row, A, x, y);
 }
 
 template <typename TA, typename TX>

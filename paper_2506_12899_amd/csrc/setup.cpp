@@ -470,6 +470,12 @@ void make_kref(const HostLevel &L, const sbm_options &o, double omega, KRef<doub
         k.g[1][a] = r.g[1][a];
         k.x[a] = r.x[a];
     }
+    for (int a = 0; a <= L.p; ++a) {
+        double den = 1.0;
+        for (int b = 0; b <= L.p; ++b)
+            if (b != a) den *= r.x[a] - r.x[b];
+        k.bw[a] = 1.0 / den;
+    }
     k.sigF = L.sigF;
     k.sigG = L.sigG;
     k.alpha = o.alpha;

@@ -81,6 +81,7 @@ void cast_kref(const KRef<double> &a, KRef<T> &b) {
         b.g[0][i] = (T)a.g[0][i];
         b.g[1][i] = (T)a.g[1][i];
         b.x[i] = (T)a.x[i];
+        b.bw[i] = (T)a.bw[i];
     }
     b.sigF = (T)a.sigF;
     b.sigG = (T)a.sigG;

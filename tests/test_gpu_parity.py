@@ -128,6 +128,31 @@ def test_vcycle_is_deterministic(pair):
     assert np.array_equal(a, b)
 
 
+# Deep hierarchies: h-coarsening continues down to the coarse_min rule
+DEEP_CASES = [
+    ("disk_q2_deep", workloads.balls([[0.03, -0.02]], [0.7]), 32, 2),
+    ("star_q1_deep", workloads.star(0.6, 0.15, 5), 64, 1),
+    ("sphere_q2_deep", workloads.balls([[0.03, -0.02, 0.01]], [0.75]), 16, 2),
+]
+
+
+@pytest.mark.parametrize("name,geo,n,p", DEEP_CASES, ids=[c[0] for c in DEEP_CASES])
+def test_vcycle_deep_hierarchy(name, geo, n, p):
+    from paper_2506_12899_amd.problem import Problem
+    dev = _gpu()
+    print(f"[parity] deep case {name} n={n} p={p}", flush=True)
+    H = mg.Hierarchy(oracle_geometry(geo), geo.dim, n, p, coarse_dofs=0)
+    pb = Problem(geo, n, p, device=0, coarse_dofs=0)
+    assert pb.n_levels == len(H.levels) >= 4
+    r = workloads.random_vector(H.fine.n_dofs, seed=63)
+    ref = H.vcycle(r)
+    z = pb.vcycle(_t(r, dev)).cpu().numpy()
+    assert _rel(z, ref) <= TOL64
+    kappa = max(np.linalg.cond(L.D).max() for L in H.levels if L.n_act)
+    z32 = pb.vcycle(_t(r, dev, torch.float32)).cpu().numpy().astype(np.float64)
+    assert _rel(z32, ref) <= max(TOL32, 5e-8 * kappa), kappa
+
+
 SOLVE_CASES = [
     ("disk32_q1", {}), ("disk32_q1", {"vcycle_fp32": 1}),
 ]
