@@ -79,7 +79,7 @@ typedef struct {
     int nu_pre, nu_post;  /* SSOR steps before / after the coarse correction (default 1, 1)   */
     int coarse_min;       /* geometric coarsening (p = 1) halves n while n is even,           */
     int coarse_dofs;      /* n/2 >= coarse_min (default 3) and the level still has more than  */
-                          /* coarse_dofs active DoFs (default 1024); the last level is solved */
+                          /* coarse_dofs active DoFs (default 2048); the last level is solved */
                           /* with a dense inverse (at most 4096 DoFs)                         */
     int vcycle_fp32;      /* sbm_solve: 0 = FP64 V-cycle, 1 = FP32 V-cycle (default 0)        */
     int allow_singular;   /* 1: shift near-singular blocks by 1e-10 |D_K| instead of failing  */

@@ -12,7 +12,7 @@ Test infrastructure only.  Follows Sec. 3 of the paper:
 
 Readings (listed in the design notes):
   * coarsening: halve n while n is even, n/2 >= coarse_min (3) and the level
-    still has more than coarse_dofs (1024) active DoFs (the coarse solver and
+    still has more than coarse_dofs (2048) active DoFs (the coarse solver and
     coarsest mesh are not specified for the experiments);
   * the smoother visits the two colours (i+j+k mod 2) in the order 0,1,1,0 per
     step; cells of one colour do not couple, so a colour is updated at once;
@@ -46,7 +46,7 @@ class Hierarchy:
     even, n/2 >= coarse_min and the current level has more than coarse_dofs
     active DoFs; the last level is solved exactly."""
 
-    def __init__(self, geom, d, n, p, coarse_min=3, coarse_dofs=1024, omega=None, nu_pre=1, nu_post=1, **kw):
+    def __init__(self, geom, d, n, p, coarse_min=3, coarse_dofs=2048, omega=None, nu_pre=1, nu_post=1, **kw):
         fine_first = [dg.Level(geom, d, n, q, **kw) for q in range(p, 0, -1)]
         nn = n
         while nn % 2 == 0 and nn // 2 >= coarse_min and fine_first[-1].n_dofs > coarse_dofs:

@@ -322,7 +322,7 @@ int sbm_default_options(int dim, int p, sbm_options *o) {
     o->nu_pre = 1;
     o->nu_post = 1;
     o->coarse_min = 3;
-    o->coarse_dofs = 1024;
+    o->coarse_dofs = 2048;
     o->vcycle_fp32 = 0;
     o->allow_singular = 0;
     o->device = 0;

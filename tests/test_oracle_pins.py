@@ -483,8 +483,11 @@ def test_level_shapes():
     assert mg.level_shapes(128, 3)[-1] == (4, 1)
     # the size rule stops at the first p = 1 level with at most coarse_dofs DoFs
     disk = geometry.Balls([[0.0, 0.0]], [0.7])
-    H = mg.Hierarchy(disk, 2, 32, 2)
+    H = mg.Hierarchy(disk, 2, 32, 2, coarse_dofs=1024)
     assert [(L.n, L.p) for L in H.levels] == [(16, 1), (32, 1), (32, 2)]
     assert H.levels[1].n_dofs > 1024 >= H.levels[0].n_dofs
+    H = mg.Hierarchy(disk, 2, 64, 2)   # default coarse_dofs = 2048
+    assert [(L.n, L.p) for L in H.levels] == [(32, 1), (64, 1), (64, 2)]
+    assert H.levels[1].n_dofs > 2048 >= H.levels[0].n_dofs
     H = mg.Hierarchy(disk, 2, 32, 1, coarse_dofs=0)
     assert [(L.n, L.p) for L in H.levels] == [(4, 1), (8, 1), (16, 1), (32, 1)]
