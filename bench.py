@@ -36,6 +36,60 @@ def apply_bytes(pb, fp32):
     return (2 * s * lay.n_dofs + 4 * 2 * d * lay.n_active + s * d * nf * lay.n_surrogate_faces)
 
 
+def smooth_pair_bytes(pb, fp32):
+    """Algorithmic bytes of a colour-0 plus a colour-1 update on the finest
+    level: each reads the whole of z (own cells and neighbour traces) and its
+    colour's b, writes its colour's z, reads its cells' neighbour table and
+    block-kind index, the inverses of its boundary cells and the shifts of
+    its surrogate faces."""
+    lay = pb.layout
+    s = 4 if fp32 else 8
+    d = pb.dim
+    nc = (pb.p + 1) ** d
+    nf = (pb.p + 1) ** (d - 1)
+    return (4 * s * lay.n_dofs + 4 * (2 * d + 1) * lay.n_active + s * nc * nc * lay.n_boundary_cells
+            + s * d * nf * lay.n_surrogate_faces)
+
+
+def time_smooth(pb, torch, fp32, reps=200, warm=10):
+    """Average launch of the finest-level colour update (colours 0 and 1 alternating)."""
+    dt = torch.float32 if fp32 else torch.float64
+    g = torch.Generator().manual_seed(2)
+    b = torch.randn(pb.n_dofs, dtype=torch.float64, generator=g).to("cuda", dt)
+    z = torch.zeros_like(b)
+    for _ in range(warm):
+        pb.colour_update(-1, 0, b, z)
+        pb.colour_update(-1, 1, b, z)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        pb.colour_update(-1, 0, b, z)
+        pb.colour_update(-1, 1, b, z)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / (2 * reps)
+
+
+def counter_traffic(workload, kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when there is none or the kernels changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_counters_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_2506_12899_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha1(f.read()).hexdigest()
+    k = rec.get("kernels", {}).get(kernel_key)
+    if rec.get("kernels_hip_sha1") != sha or k is None:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
 def time_apply(pb, torch, fp32, reps=200, warm=20):
     dt = torch.float32 if fp32 else torch.float64
     x = torch.randn(pb.n_dofs, dtype=torch.float64, generator=torch.Generator().manual_seed(1)).to("cuda", dt)
@@ -89,7 +143,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--max-iter", type=int, default=300, help="FGMRES iteration cap (failure beyond it)")
-    ap.add_argument("--profile-apply", action="store_true", help="only time finest-level applies (for profilers)")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only run finest-level applies and colour updates and a plain copy (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -108,18 +163,24 @@ def main():
     x = torch.empty_like(b)
     print(f"[bench] {prob.name}: {pb.n_dofs} DoFs, {pb.n_levels} levels, setup {setup_s:.1f} s", file=sys.stderr,
           flush=True)
-    if args.profile_apply:
-        # finest-level applies only (FP64 then FP32), for kernel traces and counters
+    if args.profile_kernels:
+        # finest-level applies and colour-update pairs (FP64 then FP32), for
+        # kernel traces and counters; then a plain 256 MiB device copy, the
+        # reference for the HBM byte counters
         ta64 = time_apply(pb, torch, False, args.apply_reps, warm=2)
         ta32 = time_apply(pb, torch, True, args.apply_reps, warm=2)
-        # a plain 256 MiB device copy: the reference for the HBM byte counters
+        ts64 = time_smooth(pb, torch, False, args.apply_reps, warm=1)
+        ts32 = time_smooth(pb, torch, True, args.apply_reps, warm=1)
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"workload": prob.name, "n_dofs": int(pb.n_dofs), "reps": args.apply_reps,
                           "apply_us_fp64": ta64 * 1e6, "apply_us_fp32": ta32 * 1e6,
-                          "bytes_fp64": apply_bytes(pb, False), "bytes_fp32": apply_bytes(pb, True)}), flush=True)
+                          "smooth_us_fp64": ts64 * 1e6, "smooth_us_fp32": ts32 * 1e6,
+                          "apply_bytes_fp64": apply_bytes(pb, False), "apply_bytes_fp32": apply_bytes(pb, True),
+                          "smooth_pair_bytes_fp64": smooth_pair_bytes(pb, False),
+                          "smooth_pair_bytes_fp32": smooth_pair_bytes(pb, True)}), flush=True)
         return
 
     def run(fp32, steps, warmup):
@@ -144,11 +205,20 @@ def main():
 
     ta64 = time_apply(pb, torch, False, args.apply_reps)
     ta32 = time_apply(pb, torch, True, args.apply_reps)
+    ts32 = time_smooth(pb, torch, True, args.apply_reps)
     by64, by32 = apply_bytes(pb, False), apply_bytes(pb, True)
+    bs32 = smooth_pair_bytes(pb, True) / 2          # per launch (average of the two colours)
     gbs64 = by64 / ta64 / 1e9
-    roof = {"bound": "hbm", "kernel": "cellop_kernel<OP_APPLY> (finest level, FP64)",
-            "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs64 / HBM_PEAK_GBS,
-            "traffic": None, "bytes_per_launch": by64, "avg_launch_us": ta64 * 1e6}
+    gbs_s = bs32 / ts32 / 1e9
+    # dominant kernel of the timed (FP32 V-cycle) solve: the finest-level colour update
+    roof = {"bound": "hbm", "kernel": "cellop_kernel<OP_SMOOTH> (finest-level colour update, FP32)",
+            "achieved": gbs_s, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs_s / HBM_PEAK_GBS,
+            "traffic": counter_traffic(prob.name, "smooth_fp32"), "bytes_per_launch": bs32,
+            "avg_launch_us": ts32 * 1e6}
+    tr_a = counter_traffic(prob.name, "apply_fp64")
+    roof_apply = {"bound": "hbm", "kernel": "cellop_kernel<OP_APPLY> (finest level, FP64)",
+                  "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs64 / HBM_PEAK_GBS,
+                  "traffic": tr_a, "bytes_per_launch": by64, "avg_launch_us": ta64 * 1e6}
     out = {
         "metric": METRIC, "value": t32, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": t32 * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
@@ -163,6 +233,7 @@ def main():
         "apply_gbs_fp32": by32 / ta32 / 1e9,
         "setup_s": setup_s,
         "roofline": roof,
+        "roofline_apply": roof_apply,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, st64["iterations"])

@@ -233,3 +233,28 @@ def install(pb, mlp):
 
 def use(pb, on):
     N.check(N.lib().sbm_use_learned(pb._h, int(bool(on))), pb._h)
+
+
+def judged_solve(pb, mlp, b, x=None, tol=1e-8, max_iter=300):
+    """Solve with and without the learned correction and keep the better run.
+
+    The plain smoother is the fallback and the judge: the learned form wins
+    only if it reaches tol in fewer iterations, or, when neither converges, a
+    lower true residual.  The winner stays enabled on pb.  Returns
+    (x, stats, choice) with choice "learned" or "plain" and stats of both."""
+    use(pb, False)
+    x0, st0 = pb.solve(b, None, tol=tol, max_iter=max_iter)
+    install(pb, mlp)
+    x1, st1 = pb.solve(b, None, tol=tol, max_iter=max_iter)
+    if st1["converged"] != st0["converged"]:
+        better = st1["converged"]
+    elif st0["converged"]:
+        better = st1["iterations"] < st0["iterations"]
+    else:
+        better = st1["rel_residual"] < st0["rel_residual"]
+    use(pb, better)
+    xb = x1 if better else x0
+    if x is not None:
+        x.copy_(xb)
+        xb = x
+    return xb, {"plain": st0, "learned": st1}, ("learned" if better else "plain")
