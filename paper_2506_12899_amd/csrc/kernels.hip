@@ -675,16 +675,103 @@ __global__ __launch_bounds__(256) void restrict_kernel(int n_coarse, int n1f, in
     restrict_dof<D, T>(gid, n1f, n1c, nch, children, rf, bc, tr.P1);
 }
 
+// The transfers that occur (h: Q1 -> Q1 with 2^d children; p: Q2 -> Q1 and
+// Q3 -> Q2 on the same cell) are instantiated with their sizes fixed, so that
+// every load of a thread is issued before the first product and the 1D
+// embedding sits in LDS (lane-indexed reads of kernel arguments would each be
+// a memory round trip).
+template <int D, int N1F, int N1C, typename T>
+__global__ __launch_bounds__(256) void prolong_fixed_kernel(int n_fine, const int *__restrict__ parent,
+                                                            const int *__restrict__ childpos,
+                                                            const T *__restrict__ zc, T *__restrict__ zf,
+                                                            TransferArgs<T> tr) {
+    constexpr int NCF = D == 2 ? N1F * N1F : N1F * N1F * N1F;
+    constexpr int NCC = D == 2 ? N1C * N1C : N1C * N1C * N1C;
+    __shared__ T sP[2][N1F][N1C];
+    for (int t = threadIdx.x; t < 2 * N1F * N1C; t += blockDim.x)
+        sP[t / (N1F * N1C)][(t / N1C) % N1F][t % N1C] = tr.P1[t / (N1F * N1C)][(t / N1C) % N1F][t % N1C];
+    const long long gid0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = gid0 < (long long)n_fine * NCF;
+    const long long gid = live ? gid0 : 0;
+    const int K = (int)(gid / NCF), i = (int)(gid % NCF);
+    const int pc = parent[K];
+    const int o = childpos[K];
+    T src[NCC];
+    const T *zp = zc + (size_t)(pc < 0 ? 0 : pc) * NCC;
+#pragma unroll
+    for (int j = 0; j < NCC; ++j) src[j] = pc < 0 ? T(0) : zp[j];
+    const T zold = zf[(size_t)K * NCF + i];
+    __syncthreads();
+    const int i0 = i % N1F, i1 = (i / N1F) % N1F, i2 = D == 3 ? i / (N1F * N1F) : 0;
+    T acc = 0;
+#pragma unroll
+    for (int j = 0; j < NCC; ++j) {
+        const int j0 = j % N1C, j1 = (j / N1C) % N1C, j2 = D == 3 ? j / (N1C * N1C) : 0;
+        T w = sP[o & 1][i0][j0] * sP[(o >> 1) & 1][i1][j1];
+        if (D == 3) w *= sP[(o >> 2) & 1][i2][j2];
+        acc += w * src[j];
+    }
+    if (live && pc >= 0) zf[(size_t)K * NCF + i] = zold + acc;
+}
+
+template <int D, int N1F, int N1C, int NCH, typename T>
+__global__ __launch_bounds__(256) void restrict_fixed_kernel(int n_coarse, const int *__restrict__ children,
+                                                             const T *__restrict__ rf, T *__restrict__ bc,
+                                                             TransferArgs<T> tr) {
+    constexpr int NCF = D == 2 ? N1F * N1F : N1F * N1F * N1F;
+    constexpr int NCC = D == 2 ? N1C * N1C : N1C * N1C * N1C;
+    __shared__ T sP[2][N1F][N1C];
+    for (int t = threadIdx.x; t < 2 * N1F * N1C; t += blockDim.x)
+        sP[t / (N1F * N1C)][(t / N1C) % N1F][t % N1C] = tr.P1[t / (N1F * N1C)][(t / N1C) % N1F][t % N1C];
+    const long long gid0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = gid0 < (long long)n_coarse * NCC;
+    const long long gid = live ? gid0 : 0;
+    const int Kc = (int)(gid / NCC), j = (int)(gid % NCC);
+    int K[NCH];
+#pragma unroll
+    for (int o = 0; o < NCH; ++o) K[o] = children[(size_t)Kc * NCH + o];
+    T src[NCH][NCF];
+#pragma unroll
+    for (int o = 0; o < NCH; ++o) {
+        const T *rp = rf + (size_t)(K[o] < 0 ? 0 : K[o]) * NCF;
+#pragma unroll
+        for (int i = 0; i < NCF; ++i) src[o][i] = K[o] < 0 ? T(0) : rp[i];
+    }
+    __syncthreads();
+    const int j0 = j % N1C, j1 = (j / N1C) % N1C, j2 = D == 3 ? j / (N1C * N1C) : 0;
+    T acc = 0;
+#pragma unroll
+    for (int o = 0; o < NCH; ++o) {
+        if (K[o] < 0) continue;
+#pragma unroll
+        for (int i = 0; i < NCF; ++i) {
+            const int i0 = i % N1F, i1 = (i / N1F) % N1F, i2 = D == 3 ? i / (N1F * N1F) : 0;
+            T w = sP[o & 1][i0][j0] * sP[(o >> 1) & 1][i1][j1];
+            if (D == 3) w *= sP[(o >> 2) & 1][i2][j2];
+            acc += w * src[o][i];
+        }
+    }
+    if (live) bc[(size_t)Kc * NCC + j] = acc;
+}
+
 template <typename T>
 int launch_prolong(int d, int n_fine, int n1f, int n1c, const int *parent, const int *childpos, const T *zc, T *zf,
                    const TransferArgs<T> &tr, hipStream_t st) {
     long long n = (long long)n_fine * (d == 2 ? n1f * n1f : n1f * n1f * n1f);
     if (n <= 0) return 0;
-    int nb = (int)((n + 255) / 256);
+    const dim3 g((unsigned)((n + 255) / 256)), bl(256);
+#define SBM_PROLONG(DD, F, C)                                                                                  \
+    if (d == DD && n1f == F && n1c == C) {                                                                    \
+        hipLaunchKernelGGL((prolong_fixed_kernel<DD, F, C, T>), g, bl, 0, st, n_fine, parent, childpos, zc, zf, tr); \
+        return hipGetLastError() == hipSuccess ? 0 : -1;                                                      \
+    }
+    SBM_PROLONG(2, 2, 2) SBM_PROLONG(2, 3, 2) SBM_PROLONG(2, 4, 3)
+    SBM_PROLONG(3, 2, 2) SBM_PROLONG(3, 3, 2) SBM_PROLONG(3, 4, 3)
+#undef SBM_PROLONG
     if (d == 2)
-        hipLaunchKernelGGL((prolong_kernel<2, T>), dim3(nb), dim3(256), 0, st, n_fine, n1f, n1c, parent, childpos, zc, zf, tr);
+        hipLaunchKernelGGL((prolong_kernel<2, T>), g, bl, 0, st, n_fine, n1f, n1c, parent, childpos, zc, zf, tr);
     else
-        hipLaunchKernelGGL((prolong_kernel<3, T>), dim3(nb), dim3(256), 0, st, n_fine, n1f, n1c, parent, childpos, zc, zf, tr);
+        hipLaunchKernelGGL((prolong_kernel<3, T>), g, bl, 0, st, n_fine, n1f, n1c, parent, childpos, zc, zf, tr);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -693,11 +780,19 @@ int launch_restrict(int d, int n_coarse, int n1f, int n1c, int nch, const int *c
                     const TransferArgs<T> &tr, hipStream_t st) {
     long long n = (long long)n_coarse * (d == 2 ? n1c * n1c : n1c * n1c * n1c);
     if (n <= 0) return 0;
-    int nb = (int)((n + 255) / 256);
+    const dim3 g((unsigned)((n + 255) / 256)), bl(256);
+#define SBM_RESTRICT(DD, F, C, H)                                                                              \
+    if (d == DD && n1f == F && n1c == C && nch == H) {                                                        \
+        hipLaunchKernelGGL((restrict_fixed_kernel<DD, F, C, H, T>), g, bl, 0, st, n_coarse, children, rf, bc, tr); \
+        return hipGetLastError() == hipSuccess ? 0 : -1;                                                      \
+    }
+    SBM_RESTRICT(2, 2, 2, 4) SBM_RESTRICT(2, 3, 2, 1) SBM_RESTRICT(2, 4, 3, 1)
+    SBM_RESTRICT(3, 2, 2, 8) SBM_RESTRICT(3, 3, 2, 1) SBM_RESTRICT(3, 4, 3, 1)
+#undef SBM_RESTRICT
     if (d == 2)
-        hipLaunchKernelGGL((restrict_kernel<2, T>), dim3(nb), dim3(256), 0, st, n_coarse, n1f, n1c, nch, children, rf, bc, tr);
+        hipLaunchKernelGGL((restrict_kernel<2, T>), g, bl, 0, st, n_coarse, n1f, n1c, nch, children, rf, bc, tr);
     else
-        hipLaunchKernelGGL((restrict_kernel<3, T>), dim3(nb), dim3(256), 0, st, n_coarse, n1f, n1c, nch, children, rf, bc, tr);
+        hipLaunchKernelGGL((restrict_kernel<3, T>), g, bl, 0, st, n_coarse, n1f, n1c, nch, children, rf, bc, tr);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template int launch_prolong<double>(int, int, int, int, const int *, const int *, const double *, double *,
