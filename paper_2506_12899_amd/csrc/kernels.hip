@@ -158,7 +158,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
     // faces) or the shift vector at the face Gauss point (surrogate
     // faces).  Loaded here, consumed after the volume stage.
     constexpr int ITEMS = (NFACE * NF + NC - 1) / NC;
-    constexpr bool PRE_B = NC <= 9;   // boundary-cell inverse column kept in registers
+    constexpr bool PRE_B = NC <= 27;  // boundary-cell inverse column kept in registers
     T raw[ITEMS][N1];
     T dqr[ITEMS][D];
     T bcol[PRE_B ? NC : 1];
@@ -426,9 +426,16 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
 #pragma unroll
                 for (int j = 0; j < (PRE_B ? NC : 1); ++j) corr += bcol[j] * sa[lc][j];
             } else {
+                // large blocks (NC = 64): the column in groups of 16 loads in flight
                 const T *Bt = a.Bbnd_t + (size_t)bi * NC * NC;
-#pragma unroll 2
-                for (int j = 0; j < NC; ++j) corr += Bt[(size_t)j * NC + i] * sa[lc][j];
+#pragma unroll 1
+                for (int j0 = 0; j0 < NC; j0 += 16) {
+                    T col[16];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) col[j] = Bt[(size_t)(j0 + j) * NC + i];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) corr += col[j] * sa[lc][j0 + j];
+                }
             }
             if (a.lw != nullptr && bi >= 0) {
                 const T *U = a.lU + (size_t)bi * NC * 4;
@@ -540,7 +547,7 @@ __device__ __forceinline__ void smooth_zero_dof(long long t, int split, const T 
         const int bi = a.bnd_of[cell];
         const T *Bt = bi < 0 ? a.Bint_t : a.Bbnd_t + (size_t)bi * NC * NC;
         T corr = 0;
-#pragma unroll 4
+#pragma unroll
         for (int j = 0; j < NC; ++j) corr += Bt[(size_t)j * NC + i] * bc[j];
         if (a.lw != nullptr && bi >= 0) {
             const T *U = a.lU + (size_t)bi * NC * 4;
