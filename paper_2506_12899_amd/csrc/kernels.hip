@@ -159,6 +159,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
     // faces).  Loaded here, consumed after the volume stage.
     constexpr int ITEMS = (NFACE * NF + NC - 1) / NC;
     constexpr bool PRE_B = NC <= 27;  // boundary-cell inverse column kept in registers
+    constexpr int SHIFT_UNROLL = NC <= 27 ? NC : 1;
     T raw[ITEMS][N1];
     T dqr[ITEMS][D];
     T bcol[PRE_B ? NC : 1];
@@ -330,12 +331,13 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
                 T wq = R.w[q1] * (D == 3 ? R.w[q2] : T(1));
                 const int layer = s ? P : 0;
                 T E = 0;
-                // boundary cells only: loops stay rolled to keep register pressure
-                // of the whole kernel low
+                // boundary cells only: the loops are unrolled (independent LDS
+                // reads in flight together) except for the largest cells, where
+                // they stay rolled to bound the register pressure
                 if (R.ext == 0) {
                     // gradient of u at the face Gauss point
                     T dk = 0, dt1 = 0, dt2 = 0;
-#pragma unroll 1
+#pragma unroll(SHIFT_UNROLL)
                     for (int j = 0; j < NF; ++j) {
                         int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
                         T s1 = R.S[q1][j1], s2 = D == 3 ? R.S[q2][j2] : T(1);
@@ -365,14 +367,14 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
                         lagrange_dev<T, N1>(R.x, R.bw, xc + dq[c], lv[c]);
                     }
                     T acc = 0, face = 0;
-#pragma unroll 1
+#pragma unroll(SHIFT_UNROLL)
                     for (int jj = 0; jj < NC; ++jj) {
                         int a0 = jj % N1, a1 = (jj / N1) % N1, a2 = D == 3 ? jj / (N1 * N1) : 0;
                         T pv = lv[0][a0] * lv[1][a1];
                         if (D == 3) pv *= lv[2][a2];
                         acc += pv * su[lc][jj];
                     }
-#pragma unroll 1
+#pragma unroll(SHIFT_UNROLL)
                     for (int j = 0; j < NF; ++j) {
                         int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
                         T sv = R.S[q1][j1] * (D == 3 ? R.S[q2][j2] : T(1));
@@ -397,7 +399,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
             T coef = -R.alpha * sg * R.g[s][m] + R.sigG * ev;
             int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
             T acc = 0;
-#pragma unroll 1
+#pragma unroll(SHIFT_UNROLL)
             for (int q = 0; q < NF; ++q) {
                 int q1 = q % N1, q2 = D == 3 ? q / N1 : 0;
                 T sv = R.S[q1][j1] * (D == 3 ? R.S[q2][j2] : T(1));
