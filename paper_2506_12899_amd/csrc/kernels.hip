@@ -160,6 +160,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
     constexpr int ITEMS = (NFACE * NF + NC - 1) / NC;
     constexpr bool PRE_B = NC <= 27;  // boundary-cell inverse column kept in registers
     constexpr int SHIFT_UNROLL = NC <= 27 ? NC : 1;
+    constexpr int CORR_UNROLL = NC <= 27 ? NC : 8;
     T raw[ITEMS][N1];
     T dqr[ITEMS][D];
     T bcol[PRE_B ? NC : 1];
@@ -422,7 +423,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
         if (live) {
             T corr = 0;
             if (bi < 0) {
-#pragma unroll 4
+#pragma unroll(CORR_UNROLL)
                 for (int j = 0; j < NC; ++j) corr += sB[j * NC + i] * sa[lc][j];
             } else if (PRE_B) {
 #pragma unroll
@@ -443,7 +444,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
                 const T *U = a.lU + (size_t)bi * NC * 4;
                 const T *V = a.lV + (size_t)bi * NC * 4;
                 T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-#pragma unroll 1
+#pragma unroll(CORR_UNROLL)
                 for (int j = 0; j < NC; ++j) {
                     T r = sa[lc][j];
                     v0 += V[j * 4 + 0] * r;
@@ -555,7 +556,7 @@ __device__ __forceinline__ void smooth_zero_dof(long long t, int split, const T 
             const T *U = a.lU + (size_t)bi * NC * 4;
             const T *V = a.lV + (size_t)bi * NC * 4;
             T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-#pragma unroll 1
+#pragma unroll 8
             for (int j = 0; j < NC; ++j) {
                 T r = bc[j];
                 v0 += V[j * 4 + 0] * r;
