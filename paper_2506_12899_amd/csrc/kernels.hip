@@ -123,7 +123,7 @@ struct CellLds {
 template <int D, int P, typename T, int OP, int NW>
 __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB, bool first, int bstart, int bend,
                                            const T *xin, T *out, const T *__restrict__ b, const CellArgs<T> &a,
-                                           const KRef<T> &R) {
+                                           const KRef<T> &R, const int *__restrict__ perm = nullptr) {
     using S = Sh<D, P>;
     constexpr int N1 = S::N1, NC = S::NC, NF = S::NF, NFACE = S::NFACE;
     auto &su = L.su;
@@ -138,8 +138,10 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
     const bool slot = lane < S::CPW * NC;
     const int lc = slot ? wave * S::CPW + lane / NC : 0;
     const int i = slot ? lane % NC : 0;
-    const int cell = bstart + lc;
-    const bool live = slot && cell < bend;
+    // with perm, batch slot e takes the cell perm[e] (-1: no cell)
+    const int slotpos = bstart + lc;
+    const int cell = perm != nullptr ? (slot && slotpos < bend ? perm[slotpos] : -1) : slotpos;
+    const bool live = slot && slotpos < bend && cell >= 0;
     wave_sync();  // the previous batch is done with this wave's LDS slices
 
     T bval = 0;
@@ -416,6 +418,11 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
         if (live) out[(size_t)cell * NC + i] = y;
     } else if (OP == OP_RESID) {
         if (live) out[(size_t)cell * NC + i] = bval - y;
+    } else if (OP == OP_RESTRICT) {
+        // the residual stays in LDS for the restriction that follows
+        wave_sync();
+        if (slot) sa[lc][i] = live ? bval - y : T(0);
+        wave_sync();
     } else {
         wave_sync();
         if (live) sa[lc][i] = bval - y;
@@ -500,13 +507,115 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
     }
 }
 
+// Residual and restriction in one launch (Sec. 3.2: the restriction is the
+// transpose of the embedding); the residual is not written to memory.
+//  h-transfer (nch = 2^d children): batches walk groups of child cells,
+//    perm[g * nch + o] (-1 for an inactive child) of the coarse cell grp[g], so
+//    that the children of a coarse cell sit in one wave; their residuals stay
+//    in LDS and the wave forms bc = sum_o E_o^T r_o.
+//  p-transfer (same cells, perm = nullptr): batches follow the whole-level
+//    batch table and every cell restricts its own residual.
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void resid_restrict_kernel(int n_coarse, int nch, int n1c,
+                                                             const int *__restrict__ perm,
+                                                             const int *__restrict__ grp, const T *xin,
+                                                             const T *__restrict__ b, T *__restrict__ bc,
+                                                             CellArgs<T> a, KRef<T> Rarg, TransferArgs<T> tr) {
+    using S = Sh<D, P>;
+    constexpr int N1 = S::N1, NC = S::NC, CPW = S::CPW, CPB = S::CPB;
+    __shared__ CellLds<D, P, T, S::WAVES> L;
+    __shared__ KRef<T> sR;
+    __shared__ T sP[2][N1][MAXN1];
+    {
+        const unsigned *src = reinterpret_cast<const unsigned *>(&Rarg);
+        unsigned *dst = reinterpret_cast<unsigned *>(&sR);
+        for (int t = threadIdx.x; t < (int)(sizeof(KRef<T>) / 4); t += blockDim.x) dst[t] = src[t];
+        for (int t = threadIdx.x; t < 2 * N1 * MAXN1; t += blockDim.x)
+            sP[t / (N1 * MAXN1)][(t / MAXN1) % N1][t % MAXN1] = tr.P1[t / (N1 * MAXN1)][(t / MAXN1) % N1][t % MAXN1];
+    }
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    int bstart, bend;
+    if (perm != nullptr) {
+        bstart = blk * CPB;
+        bend = n_coarse * nch;
+    } else {
+        bstart = a.batch_start[blk];
+        bend = min(bstart + CPB, bstart < a.split ? a.split : n_coarse);
+    }
+    cell_batch<D, P, T, OP_RESTRICT, S::WAVES>(L, nullptr, true, bstart, bend, xin, nullptr, b, a, sR, perm);
+    // coarse DoFs of this wave's parents: CPW / nch parents, ncc DoFs each
+    const int ncc = D == 2 ? n1c * n1c : n1c * n1c * n1c;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int npar = CPW / nch;
+    if (lane < npar * ncc) {
+        const int pp = lane / ncc, j = lane % ncc;
+        const int g = (bstart + wave * CPW) / nch + pp;   // group (h) or cell (p) of this parent
+        if (perm != nullptr ? g < n_coarse : g < bend) {
+            const int Kc = perm != nullptr ? grp[g] : g;
+            const int j0 = j % n1c, j1 = (j / n1c) % n1c, j2 = D == 3 ? j / (n1c * n1c) : 0;
+            T acc = 0;
+            for (int o = 0; o < nch; ++o) {
+                const int lc = wave * CPW + pp * nch + o;
+#pragma unroll
+                for (int i = 0; i < NC; ++i) {
+                    const int i0 = i % N1, i1 = (i / N1) % N1, i2 = D == 3 ? i / (N1 * N1) : 0;
+                    T w = sP[o & 1][i0][j0] * sP[(o >> 1) & 1][i1][j1];
+                    if (D == 3) w *= sP[(o >> 2) & 1][i2][j2];
+                    acc += w * L.sa[lc][i];
+                }
+            }
+            bc[(size_t)Kc * ncc + j] = acc;
+        }
+    }
+}
+
+template <int D, int P, typename T>
+static int launch_rr(int n_coarse, int nch, int n1c, const int *perm, const int *grp, const T *x, const T *b, T *bc,
+                     const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr, hipStream_t st) {
+    using S = Sh<D, P>;
+    if (n_coarse <= 0) return 0;
+    if (S::CPW % nch != 0) return -1;   // a wave must hold whole child groups
+    if (perm == nullptr && (nch != 1 || a.batch_start == nullptr)) return -1;
+    const int nb = perm != nullptr ? (int)(((long long)n_coarse * nch + S::CPB - 1) / S::CPB) : a.nbatch;
+    hipLaunchKernelGGL((resid_restrict_kernel<D, P, T>), dim3(nb), dim3(256), 0, st, n_coarse, nch, n1c, perm, grp,
+                       x, b, bc, a, R, tr);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+int launch_resid_restrict(int d, int p, int n_coarse, int nch, int n1c, const int *perm, const int *grp, const T *x,
+                          const T *b, T *bc, const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr,
+                          hipStream_t st) {
+    if (n1c < 1 || n1c > p + 1) return -1;
+    if (d == 2) {
+        if (p == 1) return launch_rr<2, 1, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
+        if (p == 2) return launch_rr<2, 2, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
+        if (p == 3) return launch_rr<2, 3, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
+    } else {
+        if (p == 1) return launch_rr<3, 1, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
+        if (p == 2) return launch_rr<3, 2, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
+        if (p == 3) return launch_rr<3, 3, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
+    }
+    return -1;
+}
+template int launch_resid_restrict<double>(int, int, int, int, int, const int *, const int *, const double *,
+                                           const double *,
+                                           double *, const CellArgs<double> &, const KRef<double> &,
+                                           const TransferArgs<double> &, hipStream_t);
+template int launch_resid_restrict<float>(int, int, int, int, int, const int *, const int *, const float *,
+                                          const float *, float *,
+                                          const CellArgs<float> &, const KRef<float> &, const TransferArgs<float> &,
+                                          hipStream_t);
+
 template <int D, int P, typename T>
 static int launch_dp(int op, int cell0, int ncells, const T *x, T *y, const T *b, const CellArgs<T> &a,
                      const KRef<T> &R, hipStream_t st) {
     if (ncells <= 0) return 0;
     using S = Sh<D, P>;
     int nb = a.batch_start != nullptr ? a.nbatch : (ncells + S::CPB - 1) / S::CPB;
-    if (op == OP_SMOOTH) nb = std::min(nb, 2048);
+    // the largest cells (64 DoFs) stage a 16-32 KB shared inverse per block: cap
+    // the grid and let each block walk several batches
+    if (op == OP_SMOOTH && S::NC > 27) nb = std::min(nb, 2048);
     if (op == OP_APPLY)
         hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_APPLY>), dim3(nb), dim3(256), 0, st, cell0, ncells, x, y, b, a, R);
     else if (op == OP_RESID)

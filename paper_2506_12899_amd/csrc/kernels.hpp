@@ -5,7 +5,7 @@
 
 namespace sbm {
 
-enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2 };
+enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2, OP_RESTRICT = 3 };
 
 template <typename T>
 struct CellArgs {
@@ -37,6 +37,13 @@ struct TransferArgs {
 template <typename T>
 int launch_cellop(int d, int p, int op, int cell0, int ncells, const T *x, T *y, const T *b, const CellArgs<T> &a,
                   const KRef<T> &R, hipStream_t st);
+// bc = R (b - A x) for the next coarser level: residual and restriction in one
+// launch (perm: child cells grouped by coarse cell, grp: the coarse cell of
+// each group; both ordered spatially)
+template <typename T>
+int launch_resid_restrict(int d, int p, int n_coarse, int nch, int n1c, const int *perm, const int *grp, const T *x,
+                          const T *b, T *bc, const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr,
+                          hipStream_t st);
 template <typename T>
 int launch_smooth_zero(int d, int p, int n_act, int split, const T *b, T *z, const CellArgs<T> &a, T omega,
                        hipStream_t st);

@@ -11,6 +11,7 @@
 // re-orthogonalisation (CGS2) in FP64 on the device, Givens rotations on the
 // host (one small device-to-host copy per iteration), stop on the true
 // relative residual.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -146,6 +147,27 @@ int upload_level(sbm_problem *pb, int l, DevLevel<T> &D) {
         if ((rc = upload(pb, &D.parent, L.parent.data(), L.parent.size()))) return rc;
         if ((rc = upload(pb, &D.childpos, L.childpos.data(), L.childpos.size()))) return rc;
         if ((rc = upload(pb, &D.children, L.children.data(), L.children.size()))) return rc;
+        {
+            // coarse cells in lexicographic order of their mesh position (both
+            // colours mixed), so that the contiguous batch range an XCD takes in
+            // the fused residual-restriction is one spatial region
+            const int nch = (int)(L.children.size() / std::max<size_t>(1, Lc.cells.size() / Lc.d));
+            std::vector<long long> key(Lc.n_act);
+            std::vector<int> ord(Lc.n_act);
+            for (int k = 0; k < Lc.n_act; ++k) {
+                long long v = 0;
+                for (int c = Lc.d - 1; c >= 0; --c) v = v * Lc.n + Lc.cells[(size_t)k * Lc.d + c];
+                key[k] = v;
+                ord[k] = k;
+            }
+            std::sort(ord.begin(), ord.end(), [&](int x, int y) { return key[x] < key[y]; });
+            std::vector<int> perm((size_t)Lc.n_act * nch);
+            for (int g = 0; g < Lc.n_act; ++g)
+                for (int o = 0; o < nch; ++o) perm[(size_t)g * nch + o] = L.children[(size_t)ord[g] * nch + o];
+            if ((rc = upload(pb, &D.rr_perm, perm.data(), perm.size())) ||
+                (rc = upload(pb, &D.rr_grp, ord.data(), ord.size())))
+                return rc;
+        }
         double P1[2][MAXN1][MAXN1];
         embedding_1d(Lc, L, P1);
         for (int o = 0; o < 2; ++o)
@@ -219,6 +241,23 @@ int restrict_to(sbm_problem *pb, int l, const T *rf, T *bc) {
     return SBM_OK;
 }
 
+// bc = R (b - A_l z): residual of level l restricted to level l - 1, one launch
+template <typename T>
+int resid_restrict(sbm_problem *pb, int l, const T *z, const T *b, T *bc) {
+    auto &Df = devlevels<T>(pb)[l];
+    auto &Dc = devlevels<T>(pb)[l - 1];
+    TransferArgs<T> tr;
+    std::memcpy(tr.P1, Df.P1, sizeof(tr.P1));
+    const int nch = pb->levels[l].ratio == 2 ? (1 << Df.d) : 1;
+    // p-transfers keep the cells: the whole-level batch table, no child lists
+    CellArgs<T> ca = cell_args(Df, false);
+    ca.batch_start = Df.batch_start;
+    ca.nbatch = Df.nbatch;
+    KCHK(launch_resid_restrict<T>(Df.d, Df.p, Dc.n_act, nch, Dc.p + 1, nch == 1 ? nullptr : Df.rr_perm,
+                                  nch == 1 ? nullptr : Df.rr_grp, z, b, bc, ca, Df.kref, tr, pb->stream));
+    return SBM_OK;
+}
+
 template <typename T>
 int prolong_add(sbm_problem *pb, int l, const T *zc, T *zf) {
     auto &Df = devlevels<T>(pb)[l];
@@ -269,9 +308,8 @@ int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z) {
     }
     for (int s = 1; s < pb->opt.nu_pre; ++s)
         if ((rc = ssor_step<T>(pb, l, b, z))) return rc;
-    if ((rc = level_apply<T>(pb, l, OP_RESID, z, D.r, b))) return rc;
     auto &Dc = devlevels<T>(pb)[l - 1];
-    if ((rc = restrict_to<T>(pb, l, D.r, Dc.b))) return rc;
+    if ((rc = resid_restrict<T>(pb, l, z, b, Dc.b))) return rc;
     if ((rc = vcycle_rec<T>(pb, l - 1, Dc.b, Dc.z))) return rc;
     if ((rc = prolong_add<T>(pb, l, Dc.z, z))) return rc;
     for (int s = 0; s < pb->opt.nu_post; ++s)
