@@ -648,26 +648,26 @@ template int launch_cellop<float>(int, int, int, int, int, const float *, float 
 // residual is b itself, so colour-0 cells get z_K = omega B_K b_K (with the
 // learned correction where present) and colour-1 cells z_K = 0.  One thread
 // per DoF; replaces clearing z plus a full colour-0 update.
-template <int D, int P, typename T>
-__device__ __forceinline__ void smooth_zero_dof(long long t, int split, const T *__restrict__ b, T *__restrict__ z,
+template <int D, int P, typename T, typename TB>
+__device__ __forceinline__ void smooth_zero_dof(long long t, int split, const TB *__restrict__ b, T *__restrict__ z,
                                                 const CellArgs<T> &a, T omega) {
     constexpr int NC = Sh<D, P>::NC;
     const int cell = (int)(t / NC), i = (int)(t % NC);
     T out = 0;
     if (cell < split) {
-        const T *bc = b + (size_t)cell * NC;
+        const TB *bc = b + (size_t)cell * NC;
         const int bi = a.bnd_of[cell];
         const T *Bt = bi < 0 ? a.Bint_t : a.Bbnd_t + (size_t)bi * NC * NC;
         T corr = 0;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) corr += Bt[(size_t)j * NC + i] * bc[j];
+        for (int j = 0; j < NC; ++j) corr += Bt[(size_t)j * NC + i] * (T)bc[j];
         if (a.lw != nullptr && bi >= 0) {
             const T *U = a.lU + (size_t)bi * NC * 4;
             const T *V = a.lV + (size_t)bi * NC * 4;
             T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
 #pragma unroll 8
             for (int j = 0; j < NC; ++j) {
-                T r = bc[j];
+                T r = (T)bc[j];
                 v0 += V[j * 4 + 0] * r;
                 v1 += V[j * 4 + 1] * r;
                 v2 += V[j * 4 + 2] * r;
@@ -681,41 +681,48 @@ __device__ __forceinline__ void smooth_zero_dof(long long t, int split, const T 
     z[t] = out;
 }
 
-template <int D, int P, typename T>
-__global__ __launch_bounds__(256) void smooth_zero_kernel(int n_act, int split, const T *__restrict__ b,
-                                                          T *__restrict__ z, CellArgs<T> a, T omega) {
+// bcopy (optional): the right-hand side in the cycle precision, written as it
+// is read (the FP32 cycle takes its FP64 input here instead of a cast kernel)
+template <int D, int P, typename T, typename TB>
+__global__ __launch_bounds__(256) void smooth_zero_kernel(int n_act, int split, const TB *__restrict__ b,
+                                                          T *__restrict__ bcopy, T *__restrict__ z, CellArgs<T> a,
+                                                          T omega) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)n_act * Sh<D, P>::NC) return;
-    smooth_zero_dof<D, P, T>(t, split, b, z, a, omega);
+    if (bcopy != nullptr) bcopy[t] = (T)b[t];
+    smooth_zero_dof<D, P, T, TB>(t, split, b, z, a, omega);
 }
 
-template <int D, int P, typename T>
-static int launch_sz(int n_act, int split, const T *b, T *z, const CellArgs<T> &a, T omega, hipStream_t st) {
+template <int D, int P, typename T, typename TB>
+static int launch_sz(int n_act, int split, const TB *b, T *bcopy, T *z, const CellArgs<T> &a, T omega,
+                     hipStream_t st) {
     long long n = (long long)n_act * Sh<D, P>::NC;
     if (n <= 0) return 0;
-    hipLaunchKernelGGL((smooth_zero_kernel<D, P, T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n_act,
-                       split, b, z, a, omega);
+    hipLaunchKernelGGL((smooth_zero_kernel<D, P, T, TB>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n_act,
+                       split, b, bcopy, z, a, omega);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <typename T>
-int launch_smooth_zero(int d, int p, int n_act, int split, const T *b, T *z, const CellArgs<T> &a, T omega,
+template <typename T, typename TB>
+int launch_smooth_zero(int d, int p, int n_act, int split, const TB *b, T *bcopy, T *z, const CellArgs<T> &a, T omega,
                        hipStream_t st) {
     if (d == 2) {
-        if (p == 1) return launch_sz<2, 1, T>(n_act, split, b, z, a, omega, st);
-        if (p == 2) return launch_sz<2, 2, T>(n_act, split, b, z, a, omega, st);
-        if (p == 3) return launch_sz<2, 3, T>(n_act, split, b, z, a, omega, st);
+        if (p == 1) return launch_sz<2, 1, T, TB>(n_act, split, b, bcopy, z, a, omega, st);
+        if (p == 2) return launch_sz<2, 2, T, TB>(n_act, split, b, bcopy, z, a, omega, st);
+        if (p == 3) return launch_sz<2, 3, T, TB>(n_act, split, b, bcopy, z, a, omega, st);
     } else {
-        if (p == 1) return launch_sz<3, 1, T>(n_act, split, b, z, a, omega, st);
-        if (p == 2) return launch_sz<3, 2, T>(n_act, split, b, z, a, omega, st);
-        if (p == 3) return launch_sz<3, 3, T>(n_act, split, b, z, a, omega, st);
+        if (p == 1) return launch_sz<3, 1, T, TB>(n_act, split, b, bcopy, z, a, omega, st);
+        if (p == 2) return launch_sz<3, 2, T, TB>(n_act, split, b, bcopy, z, a, omega, st);
+        if (p == 3) return launch_sz<3, 3, T, TB>(n_act, split, b, bcopy, z, a, omega, st);
     }
     return -1;
 }
-template int launch_smooth_zero<double>(int, int, int, int, const double *, double *, const CellArgs<double> &,
-                                        double, hipStream_t);
-template int launch_smooth_zero<float>(int, int, int, int, const float *, float *, const CellArgs<float> &, float,
-                                       hipStream_t);
+template int launch_smooth_zero<double, double>(int, int, int, int, const double *, double *, double *,
+                                                const CellArgs<double> &, double, hipStream_t);
+template int launch_smooth_zero<float, float>(int, int, int, int, const float *, float *, float *,
+                                              const CellArgs<float> &, float, hipStream_t);
+template int launch_smooth_zero<float, double>(int, int, int, int, const double *, float *, float *,
+                                               const CellArgs<float> &, float, hipStream_t);
 
 // --------------------------------------------------------------------------
 // Transfers (Sec. 3.2): prolongation = embedding of the coarse cell polynomial

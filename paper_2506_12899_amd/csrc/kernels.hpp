@@ -44,8 +44,10 @@ template <typename T>
 int launch_resid_restrict(int d, int p, int n_coarse, int nch, int n1c, const int *perm, const int *grp, const T *x,
                           const T *b, T *bc, const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr,
                           hipStream_t st);
-template <typename T>
-int launch_smooth_zero(int d, int p, int n_act, int split, const T *b, T *z, const CellArgs<T> &a, T omega,
+// first colour-0 update from z = 0; b may be FP64 for an FP32 cycle, bcopy
+// (optional) receives b in the cycle precision
+template <typename T, typename TB>
+int launch_smooth_zero(int d, int p, int n_act, int split, const TB *b, T *bcopy, T *z, const CellArgs<T> &a, T omega,
                        hipStream_t st);
 template <typename T>
 int launch_prolong(int d, int n_fine, int n1f, int n1c, const int *parent, const int *childpos, const T *zc, T *zf,

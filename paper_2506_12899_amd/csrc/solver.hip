@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -273,15 +274,23 @@ int prolong_add(sbm_problem *pb, int l, const T *zc, T *zf) {
 // cell, and nothing it depends on changes before the repeated colour-1 update
 // (cells of one colour do not couple), so that update adds zero up to rounding
 // and is skipped.  With omega != 1 or the learned correction it is kept.
+// from_zero: z starts at zero; with b64 (FP32 cycle only) the right-hand side
+// is read in FP64 and its FP32 copy written to b on the way.
 template <typename T>
-int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false) {
+int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false, const double *b64 = nullptr) {
     const bool learned_here = pb->learned_on && l == (int)pb->levels.size() - 1;
     const bool skip_repeat = pb->opt.omega == 1.0 && !learned_here;
     int rc;
     if (from_zero) {
         auto &D = devlevels<T>(pb)[l];
-        KCHK(launch_smooth_zero<T>(D.d, D.p, D.n_act, D.n_col0, b, z, cell_args(D, learned_here && D.lw != nullptr),
-                                   D.kref.omega, pb->stream));
+        const CellArgs<T> ca = cell_args(D, learned_here && D.lw != nullptr);
+        if (b64 != nullptr) {
+            KCHK((launch_smooth_zero<T, double>(D.d, D.p, D.n_act, D.n_col0, b64, const_cast<T *>(b), z, ca,
+                                                D.kref.omega, pb->stream)));
+        } else {
+            KCHK((launch_smooth_zero<T, T>(D.d, D.p, D.n_act, D.n_col0, b, (T *)nullptr, z, ca, D.kref.omega,
+                                           pb->stream)));
+        }
     } else if ((rc = colour_update<T>(pb, l, 0, b, z))) {
         return rc;
     }
@@ -290,10 +299,16 @@ int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false) 
     return colour_update<T>(pb, l, 0, b, z);
 }
 
+// b64 (FP32 cycle at the finest level only): the FP64 right-hand side; b is
+// then the cycle's own FP32 buffer, filled by the first smoothing kernel.
 template <typename T>
-int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z) {
+int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z, const double *b64 = nullptr) {
     auto &D = devlevels<T>(pb)[l];
     if (l == 0) {
+        if constexpr (std::is_same<T, float>::value) {
+            // a one-level hierarchy: the FP32 copy of the right-hand side first
+            if (b64 != nullptr) KCHK(launch_cast_d2f(pb->coarse.n, b64, const_cast<float *>(b), pb->stream));
+        }
         // the coarsest problem is tiny and can be badly conditioned: the FP32
         // cycle also solves it with the FP64 inverse
         KCHK((launch_dense_gemv<double, T>(pb->coarse.n, pb->coarse.Ainv64, b, z, pb->stream)));
@@ -302,8 +317,11 @@ int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z) {
     int rc;
     if (pb->opt.nu_pre > 0) {
         // z starts at zero: the first colour-0 update needs no operator application
-        if ((rc = ssor_step<T>(pb, l, b, z, true))) return rc;
+        if ((rc = ssor_step<T>(pb, l, b, z, true, b64))) return rc;
     } else {
+        if constexpr (std::is_same<T, float>::value) {
+            if (b64 != nullptr) KCHK(launch_cast_d2f(D.n_act * (long long)D.nc, b64, const_cast<float *>(b), pb->stream));
+        }
         KCHK(launch_fill<T>((long long)D.n_act * D.nc, z, T(0), pb->stream));
     }
     for (int s = 1; s < pb->opt.nu_pre; ++s)
@@ -785,8 +803,8 @@ int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, in
         while (j < m && its < max_iter) {
             double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
             if (f32) {
-                KCHK(launch_cast_d2f(n, vj, pb->f32_in, s));
-                if ((rc = vcycle_rec<float>(pb, lf, pb->f32_in, pb->f32_out))) return rc;
+                // the cycle reads v_j in FP64 and keeps its own FP32 copy
+                if ((rc = vcycle_rec<float>(pb, lf, pb->f32_in, pb->f32_out, vj))) return rc;
                 KCHK(launch_cast_f2d(n, pb->f32_out, zj, s));
             } else {
                 if ((rc = vcycle_rec<double>(pb, lf, vj, zj))) return rc;
