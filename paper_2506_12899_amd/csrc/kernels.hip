@@ -1087,13 +1087,10 @@ static int gs_grid(long long n) {
 // in cache) with a zero weight or an unused sum, so every load of an element
 // step is unconditional and all of them are in flight together.
 static int gs_bucket(int m) { return m == 0 ? 0 : m <= 4 ? 4 : m <= 8 ? 8 : m <= 16 ? 16 : 32; }
-// the 32-vector pass runs 512-thread blocks so that it has 256 registers per lane
-template <int MB>
-constexpr int gs_threads() { return MB > 16 ? 512 : GS_THREADS; }
 
 // partials of V_i . w (i < m) and of w . w (slot m)
 template <int MB>
-__global__ __launch_bounds__(gs_threads<MB>()) void gs_dots_kernel(long long n, int m, const double *__restrict__ V,
+__global__ __launch_bounds__(GS_THREADS) void gs_dots_kernel(long long n, int m, const double *__restrict__ V,
                                                              const double *__restrict__ w, double *__restrict__ part) {
     double acc[GS_MAXV];
 #pragma unroll
@@ -1109,53 +1106,71 @@ __global__ __launch_bounds__(gs_threads<MB>()) void gs_dots_kernel(long long n, 
 #pragma unroll
     for (int i = 0; i < GS_MAXV; ++i)
         if (i == m) acc[i] = ww;
-    block_partials<gs_threads<MB>() / 64>(acc, m + 1, part);
+    block_partials<GS_WAVES>(acc, m + 1, part);
 }
 
 // h = sums of the nblk_in x (m + 1) partials hpart (block 0 also stores all
 // m + 1 of them in hout); w <- w - sum_i h[i] V_i; partials of V_i . w (i < m)
 // and of w . w (slot m)
 template <int MB>
-__global__ __launch_bounds__(gs_threads<MB>()) void gs_axpy_dots_kernel(long long n, int m, const double *__restrict__ V,
+__global__ __launch_bounds__(GS_THREADS) void gs_axpy_dots_kernel(long long n, int m, const double *__restrict__ V,
                                                                   const double *__restrict__ hpart, int nblk_in,
                                                                   double *__restrict__ hout, double *__restrict__ w,
                                                                   double *__restrict__ part) {
     __shared__ double hs[GS_MAXV];
-    sum_partials<gs_threads<MB>() / 64>(hpart, nblk_in, m + 1, hs);
+    sum_partials<GS_WAVES>(hpart, nblk_in, m + 1, hs);
     __syncthreads();
     if (blockIdx.x == 0 && (int)threadIdx.x <= m) hout[threadIdx.x] = hs[threadIdx.x];
-    // up to 16 vectors the weights and the loaded elements stay in registers;
-    // beyond that the weights are read from LDS and the elements loaded again
-    // for the second sum (cache hits), which avoids spills
-    constexpr bool KEEP = MB <= 16;
-    if (!KEEP && (int)threadIdx.x < GS_MAXV && (int)threadIdx.x >= m) hs[threadIdx.x] = 0.0;
-    __syncthreads();
-    double hh[KEEP && MB > 0 ? MB : 1], acc[GS_MAXV];
+    // (instantiated up to 16 vectors: weights and loaded elements stay in registers)
+    static_assert(MB <= 16, "larger bases use gs_axpy_kernel + gs_dots_kernel");
+    double hh[MB > 0 ? MB : 1], acc[GS_MAXV];
 #pragma unroll
-    for (int i = 0; i < (KEEP ? MB : 0); ++i) hh[i] = i < m ? hs[i] : 0.0;
+    for (int i = 0; i < MB; ++i) hh[i] = i < m ? hs[i] : 0.0;
 #pragma unroll
     for (int i = 0; i < GS_MAXV; ++i) acc[i] = 0.0;
     double ww = 0.0;
     const long long st = (long long)gridDim.x * blockDim.x;
     for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
-        double vk[KEEP && MB > 0 ? MB : 1];
+        double vk[MB > 0 ? MB : 1];
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
-            const double v = V[(size_t)(i < m ? i : m - 1) * n + k];
-            if (KEEP) vk[i] = v;
-            s += (KEEP ? hh[i] : hs[i]) * v;
+            vk[i] = V[(size_t)(i < m ? i : m - 1) * n + k];
+            s += hh[i] * vk[i];
         }
         const double wk = w[k] - s;
         w[k] = wk;
 #pragma unroll
-        for (int i = 0; i < MB; ++i) acc[i] += (KEEP ? vk[i] : V[(size_t)(i < m ? i : m - 1) * n + k]) * wk;
+        for (int i = 0; i < MB; ++i) acc[i] += vk[i] * wk;
         ww += wk * wk;
     }
 #pragma unroll
     for (int i = 0; i < GS_MAXV; ++i)
         if (i == m) acc[i] = ww;
-    block_partials<gs_threads<MB>() / 64>(acc, m + 1, part);
+    block_partials<GS_WAVES>(acc, m + 1, part);
+}
+
+// h = sums of the partials hpart (block 0 stores them in hout); w <- w - V h.
+// The subtraction of larger bases (17..31 vectors), whose dots then follow in
+// gs_dots_kernel: two streaming launches instead of one that would spill.
+template <int MB>
+__global__ __launch_bounds__(GS_THREADS) void gs_axpy_kernel(long long n, int m, const double *__restrict__ V,
+                                                             const double *__restrict__ hpart, int nblk_in,
+                                                             double *__restrict__ hout, double *__restrict__ w) {
+    __shared__ double hs[GS_MAXV];
+    sum_partials<GS_WAVES>(hpart, nblk_in, m + 1, hs);
+    __syncthreads();
+    if (blockIdx.x == 0 && (int)threadIdx.x <= m) hout[threadIdx.x] = hs[threadIdx.x];
+    double hh[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) hh[i] = i < m ? hs[i] : 0.0;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) s += hh[i] * V[(size_t)(i < m ? i : m - 1) * n + k];
+        w[k] -= s;
+    }
 }
 
 __global__ __launch_bounds__(GS_THREADS) void gs_reduce_kernel(const double *__restrict__ part, int nblk, int nv,
@@ -1165,13 +1180,13 @@ __global__ __launch_bounds__(GS_THREADS) void gs_reduce_kernel(const double *__r
 
 int launch_gs_dots(long long n, int m, const double *V, const double *w, double *part, hipStream_t st) {
     if (m < 0 || m > GS_MAXV - 1 || n < 0) return -1;
-    const dim3 g(gs_grid(n)), bl(GS_THREADS), bl32(gs_threads<32>());
+    const dim3 g(gs_grid(n)), bl(GS_THREADS);
     switch (gs_bucket(m)) {
         case 0: hipLaunchKernelGGL(gs_dots_kernel<0>, g, bl, 0, st, n, m, V, w, part); break;
         case 4: hipLaunchKernelGGL(gs_dots_kernel<4>, g, bl, 0, st, n, m, V, w, part); break;
         case 8: hipLaunchKernelGGL(gs_dots_kernel<8>, g, bl, 0, st, n, m, V, w, part); break;
         case 16: hipLaunchKernelGGL(gs_dots_kernel<16>, g, bl, 0, st, n, m, V, w, part); break;
-        default: hipLaunchKernelGGL(gs_dots_kernel<32>, g, bl32, 0, st, n, m, V, w, part);
+        default: hipLaunchKernelGGL(gs_dots_kernel<32>, g, bl, 0, st, n, m, V, w, part);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -1180,12 +1195,14 @@ int launch_gs_axpy_dots(long long n, int m, const double *V, const double *hpart
                         double *part, hipStream_t st) {
     if (m < 1 || m > GS_MAXV - 1 || n < 0) return -1;
     const int nb = gs_grid(n);
-    const dim3 g(nb), bl(GS_THREADS), bl32(gs_threads<32>());
+    const dim3 g(nb), bl(GS_THREADS);
     switch (gs_bucket(m)) {
         case 4: hipLaunchKernelGGL(gs_axpy_dots_kernel<4>, g, bl, 0, st, n, m, V, hpart, nb, hout, w, part); break;
         case 8: hipLaunchKernelGGL(gs_axpy_dots_kernel<8>, g, bl, 0, st, n, m, V, hpart, nb, hout, w, part); break;
         case 16: hipLaunchKernelGGL(gs_axpy_dots_kernel<16>, g, bl, 0, st, n, m, V, hpart, nb, hout, w, part); break;
-        default: hipLaunchKernelGGL(gs_axpy_dots_kernel<32>, g, bl32, 0, st, n, m, V, hpart, nb, hout, w, part);
+        default:
+            hipLaunchKernelGGL(gs_axpy_kernel<32>, g, bl, 0, st, n, m, V, hpart, nb, hout, w);
+            hipLaunchKernelGGL(gs_dots_kernel<32>, g, bl, 0, st, n, m, V, w, part);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
