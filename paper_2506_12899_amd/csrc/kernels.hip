@@ -160,8 +160,12 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
     // faces) or the shift vector at the face Gauss point (surrogate
     // faces).  Loaded here, consumed after the volume stage.
     constexpr int ITEMS = (NFACE * NF + NC - 1) / NC;
-    constexpr bool PRE_B = NC <= 27;  // boundary-cell inverse column kept in registers
-    constexpr int SHIFT_UNROLL = NC <= 27 ? NC : 1;
+    // Register budget (measured on the 3D Q2 solve): the boundary-cell inverse
+    // column stays in registers up to 16 entries; the shift-stage loops unroll
+    // fully up to 16 DoFs per cell, partly for 27 (by 3 in FP32, 9 in FP64) and
+    // not for 64, trading the latency of dependent LDS reads against occupancy.
+    constexpr bool PRE_B = NC <= 16;
+    constexpr int SHIFT_UNROLL = NC <= 16 ? NC : (NC <= 27 ? (sizeof(T) == 4 ? 3 : 9) : 1);
     constexpr int CORR_UNROLL = NC <= 27 ? NC : 8;
     T raw[ITEMS][N1];
     T dqr[ITEMS][D];
@@ -436,15 +440,17 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
 #pragma unroll
                 for (int j = 0; j < (PRE_B ? NC : 1); ++j) corr += bcol[j] * sa[lc][j];
             } else {
-                // large blocks (NC = 64): the column in groups of 16 loads in flight
+                // large blocks: the column in groups of 16 loads in flight (the
+                // last group is cut at NC)
                 const T *Bt = a.Bbnd_t + (size_t)bi * NC * NC;
 #pragma unroll 1
                 for (int j0 = 0; j0 < NC; j0 += 16) {
                     T col[16];
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) col[j] = Bt[(size_t)(j0 + j) * NC + i];
+                    for (int j = 0; j < 16; ++j) col[j] = j0 + j < NC ? Bt[(size_t)(j0 + j) * NC + i] : T(0);
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) corr += col[j] * sa[lc][j0 + j];
+                    for (int j = 0; j < 16; ++j)
+                        if (j0 + j < NC) corr += col[j] * sa[lc][j0 + j];
                 }
             }
             if (a.lw != nullptr && bi >= 0) {
