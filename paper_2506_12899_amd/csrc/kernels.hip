@@ -14,7 +14,8 @@
 //
 // Thread mapping: one thread per DoF, 64 / (p+1)^d cells per wave (a cell
 // never straddles a wave, so the cell's threads exchange LDS data without
-// block barriers), 4 waves per block; cell data staged in LDS.  The
+// block barriers), 2 waves per block (4 for 64-DoF cells); cell data staged in
+// LDS.  The
 // block index is remapped so that each of the 8 XCDs works on a contiguous
 // range of cells (neighbour traces then hit that XCD's L2).
 #include "kernels.hpp"
@@ -27,7 +28,7 @@ struct Sh {
     static constexpr int NC = D == 2 ? N1 * N1 : N1 * N1 * N1;
     static constexpr int NF = D == 2 ? N1 : N1 * N1;
     static constexpr int CPW = 64 / NC;
-    static constexpr int WAVES = 4;
+    static constexpr int WAVES = cell_waves(NC);
     static constexpr int CPB = CPW * WAVES;
     static constexpr int NFACE = 2 * D;
 };
@@ -474,7 +475,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
 }
 
 template <int D, int P, typename T, int OP>
-__global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, const T *xin, T *out,
+__global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void cellop_kernel(int cell0, int ncells, const T *xin, T *out,
                                                     const T *__restrict__ b, CellArgs<T> a, KRef<T> Rarg) {
     using S = Sh<D, P>;
     constexpr int NC = S::NC, CPB = S::CPB;
@@ -522,7 +523,7 @@ __global__ __launch_bounds__(256) void cellop_kernel(int cell0, int ncells, cons
 //  p-transfer (same cells, perm = nullptr): batches follow the whole-level
 //    batch table and every cell restricts its own residual.
 template <int D, int P, typename T>
-__global__ __launch_bounds__(256) void resid_restrict_kernel(int n_coarse, int nch, int n1c,
+__global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void resid_restrict_kernel(int n_coarse, int nch, int n1c,
                                                              const int *__restrict__ perm,
                                                              const int *__restrict__ grp, const T *xin,
                                                              const T *__restrict__ b, T *__restrict__ bc,
@@ -583,7 +584,7 @@ static int launch_rr(int n_coarse, int nch, int n1c, const int *perm, const int 
     if (S::CPW % nch != 0) return -1;   // a wave must hold whole child groups
     if (perm == nullptr && (nch != 1 || a.batch_start == nullptr)) return -1;
     const int nb = perm != nullptr ? (int)(((long long)n_coarse * nch + S::CPB - 1) / S::CPB) : a.nbatch;
-    hipLaunchKernelGGL((resid_restrict_kernel<D, P, T>), dim3(nb), dim3(256), 0, st, n_coarse, nch, n1c, perm, grp,
+    hipLaunchKernelGGL((resid_restrict_kernel<D, P, T>), dim3(nb), dim3(64 * S::WAVES), 0, st, n_coarse, nch, n1c, perm, grp,
                        x, b, bc, a, R, tr);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -623,11 +624,11 @@ static int launch_dp(int op, int cell0, int ncells, const T *x, T *y, const T *b
     // the grid and let each block walk several batches
     if (op == OP_SMOOTH && S::NC > 27) nb = std::min(nb, 2048);
     if (op == OP_APPLY)
-        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_APPLY>), dim3(nb), dim3(256), 0, st, cell0, ncells, x, y, b, a, R);
+        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_APPLY>), dim3(nb), dim3(64 * S::WAVES), 0, st, cell0, ncells, x, y, b, a, R);
     else if (op == OP_RESID)
-        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_RESID>), dim3(nb), dim3(256), 0, st, cell0, ncells, x, y, b, a, R);
+        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_RESID>), dim3(nb), dim3(64 * S::WAVES), 0, st, cell0, ncells, x, y, b, a, R);
     else
-        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_SMOOTH>), dim3(nb), dim3(256), 0, st, cell0, ncells, x, y, b, a, R);
+        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_SMOOTH>), dim3(nb), dim3(64 * S::WAVES), 0, st, cell0, ncells, x, y, b, a, R);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -23,10 +23,15 @@ struct CellArgs {
     int nbatch, split;
 };
 
-// cells per block of the cell kernels (4 waves, 64 / (p+1)^d cells per wave)
+// waves per block of the cell kernels for cells of nc DoFs (measured: two
+// waves, except four for 64-DoF cells, whose blocks stage a large shared
+// inverse)
+constexpr int cell_waves(int nc) { return nc >= 64 ? 4 : 2; }
+
+// cells per block of the cell kernels (cell_waves waves, 64 / (p+1)^d cells per wave)
 inline int cells_per_block(int d, int p) {
     int nc = d == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
-    return 4 * (64 / nc);
+    return cell_waves(nc) * (64 / nc);
 }
 
 template <typename T>
