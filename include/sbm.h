@@ -83,6 +83,11 @@ typedef struct {
                           /* with a dense inverse (at most 4096 DoFs)                         */
     int vcycle_fp32;      /* sbm_solve: 0 = FP64 V-cycle, 1 = FP32 V-cycle (default 0)        */
     int allow_singular;   /* 1: shift near-singular blocks by 1e-10 |D_K| instead of failing  */
+    int fuse_transfers;   /* V-cycle launches (same arithmetic either way).  1 (default): the
+                             residual-restriction kernel also forms the coarser level's first
+                             colour-0 update from zero, and the last colour updates of a
+                             level add its final z into the finer level (the FP32 cycle's
+                             finest level writes z in FP64 there).  0: separate kernels   */
     int device;           /* HIP device ordinal (default 0); < 0 = host-only setup for tests:
                              no device data, the device entry points return SBM_EINVAL     */
     void *stream;         /* hipStream_t for all work (default NULL = null stream)            */

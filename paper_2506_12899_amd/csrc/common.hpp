@@ -117,6 +117,7 @@ struct DevLevel {
     int *children = nullptr;
     int *rr_perm = nullptr;   // child cells of the coarse cells in spatial order of the coarse cells
     int *rr_grp = nullptr;    // the coarse cell of each group of children in rr_perm
+    int *rr_gbnd = nullptr;   // bnd_of of that coarse cell (coarse level's block index, -1: interior)
     T P1[2][MAXN1][MAXN1];    // 1D embedding coarse->fine per child offset, [o][a_fine][b_coarse]
     int pc = 1;               // coarse degree for the transfer
     KRef<T> kref;

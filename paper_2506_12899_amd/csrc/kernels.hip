@@ -18,6 +18,8 @@
 // LDS.  The
 // block index is remapped so that each of the 8 XCDs works on a contiguous
 // range of cells (neighbour traces then hit that XCD's L2).
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace sbm {
@@ -121,11 +123,22 @@ struct CellLds {
 // batch costs three dependent memory round trips (cell data; neighbour traces,
 // shift vectors and the boundary-cell inverse; the store) rather than one per
 // stage: small levels are bound by this latency.
-template <int D, int P, typename T, int OP, int NW>
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+// EMIT (OP_SMOOTH only): see EmitArgs; e is an EmitArgs<T> unless EMIT_NONE,
+// sP the LDS copy of the fine-by-coarse 1D embedding [2][N1E][N1].  hook()
+// runs once the cell data have arrived, before the neighbour loads: a caller
+// issues loads there whose addresses depend on loads it issued before the batch.
+template <int D, int P, typename T, int OP, int NW, int EMIT = EMIT_NONE, typename EA = int, typename Hook = NoHook>
 __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB, bool first, int bstart, int bend,
                                            const T *xin, T *out, const T *__restrict__ b, const CellArgs<T> &a,
-                                           const KRef<T> &R, const int *__restrict__ perm = nullptr) {
+                                           const KRef<T> &R, const int *__restrict__ perm = nullptr,
+                                           const EA &e = EA(), const T *sP = nullptr, Hook hook = Hook()) {
     using S = Sh<D, P>;
+    static_assert(EMIT == EMIT_NONE || OP == OP_SMOOTH, "only the smoother sends values on");
+    static_assert(EMIT != EMIT_H || P == 1, "h-transfers are between Q1 levels");
     constexpr int N1 = S::N1, NC = S::NC, NF = S::NF, NFACE = S::NFACE;
     auto &su = L.su;
     auto &sa = L.sa;
@@ -153,8 +166,29 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
         if (OP != OP_APPLY) bval = b[(size_t)cell * NC + i];
         if (OP == OP_SMOOTH) bi = a.bnd_of[cell];
     }
+    // emission: the fine cell this thread writes (h: child i of the cell; p:
+    // the same cell, outputs i, i + NC, ...) and its old values
+    constexpr bool EPRO = EMIT == EMIT_H || EMIT == EMIT_P;
+    constexpr int N1E = EMIT == EMIT_P ? N1 + 1 : N1;
+    constexpr int NCE = D == 2 ? N1E * N1E : N1E * N1E * N1E;
+    constexpr int NOUT = EMIT == EMIT_H ? NCE : (NCE + NC - 1) / NC;
+    int efc = -1;
+    T ezf[EPRO ? NOUT : 1];
+    if constexpr (EPRO) {
+        if (live) efc = EMIT == EMIT_H ? e.children[(size_t)cell * NC + i] : e.children[cell];
+    }
     wave_sync();
     if (first) __syncthreads();   // R and sB staged
+    hook();
+    if constexpr (EPRO) {
+        if (efc >= 0) {
+#pragma unroll
+            for (int k = 0; k < NOUT; ++k) {
+                const int ao = EMIT == EMIT_H ? k : i + k * NC;
+                ezf[k] = ao < NCE ? e.zf[(size_t)efc * NCE + ao] : T(0);
+            }
+        }
+    }
 
     // Face items (face f, tangential index j) handled by this thread: the
     // neighbour's nodes on the line through the face point (interior
@@ -432,6 +466,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
         wave_sync();
         if (live) sa[lc][i] = bval - y;
         wave_sync();
+        T xnew = 0;
         if (live) {
             T corr = 0;
             if (bi < 0) {
@@ -469,19 +504,60 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
                 corr += U[i * 4 + 0] * v0 + U[i * 4 + 1] * v1 + U[i * 4 + 2] * v2 + U[i * 4 + 3] * v3;
                 corr *= a.lw[bi];
             }
-            out[(size_t)cell * NC + i] = su[lc][i] + R.omega * corr;
+            xnew = su[lc][i] + R.omega * corr;
+            out[(size_t)cell * NC + i] = xnew;
+            if constexpr (EMIT == EMIT_F64) e.z64[(size_t)cell * NC + i] = (double)xnew;
+        }
+        if constexpr (EPRO) {
+            // the cell's new values to all its lanes, then zf += E z (Sec. 3.2
+            // embedding, same products and order as the prolongation kernel)
+            wave_sync();
+            if (live) sb[lc][i] = xnew;
+            wave_sync();
+            if (efc >= 0) {
+                const int o = EMIT == EMIT_H ? i : 0;
+#pragma unroll
+                for (int k = 0; k < NOUT; ++k) {
+                    const int ao = EMIT == EMIT_H ? k : i + k * NC;
+                    if (ao < NCE) {
+                        const int a0 = ao % N1E, a1 = (ao / N1E) % N1E, a2 = D == 3 ? ao / (N1E * N1E) : 0;
+                        T acc = 0;
+#pragma unroll
+                        for (int j = 0; j < NC; ++j) {
+                            const int j0 = j % N1, j1 = (j / N1) % N1, j2 = D == 3 ? j / (N1 * N1) : 0;
+                            T w = sP[((o & 1) * N1E + a0) * N1 + j0] * sP[(((o >> 1) & 1) * N1E + a1) * N1 + j1];
+                            if (D == 3) w *= sP[(((o >> 2) & 1) * N1E + a2) * N1 + j2];
+                            acc += w * sb[lc][j];
+                        }
+                        e.zf[(size_t)efc * NCE + ao] = ezf[k] + acc;
+                    }
+                }
+            }
         }
     }
 }
 
-template <int D, int P, typename T, int OP>
+template <typename T, int EMIT>
+struct EmitParam {
+    using type = EmitArgs<T>;
+};
+template <typename T>
+struct EmitParam<T, EMIT_NONE> {
+    using type = int;
+};
+
+template <int D, int P, typename T, int OP, int EMIT = EMIT_NONE>
 __global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void cellop_kernel(int cell0, int ncells, const T *xin, T *out,
-                                                    const T *__restrict__ b, CellArgs<T> a, KRef<T> Rarg) {
+                                                    const T *__restrict__ b, CellArgs<T> a, KRef<T> Rarg,
+                                                    typename EmitParam<T, EMIT>::type e) {
     using S = Sh<D, P>;
-    constexpr int NC = S::NC, CPB = S::CPB;
+    constexpr int N1 = S::N1, NC = S::NC, CPB = S::CPB;
+    constexpr bool EPRO = EMIT == EMIT_H || EMIT == EMIT_P;
+    constexpr int N1E = EMIT == EMIT_P ? N1 + 1 : N1;
     __shared__ CellLds<D, P, T, S::WAVES> L;
     __shared__ T sB[OP == OP_SMOOTH ? NC * NC : 1];  // shared interior-cell inverse
     __shared__ KRef<T> sR;
+    __shared__ T sP[EPRO ? 2 * N1E * N1 : 1];     // embedding for the emission
     // The reference data are indexed per lane; read from the kernel arguments
     // every access would be a memory round trip on the critical path.
     {
@@ -492,14 +568,21 @@ __global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void cellop_kernel(int cell
     }
     if (OP == OP_SMOOTH)
         for (int t = threadIdx.x; t < NC * NC; t += blockDim.x) sB[t] = a.Bint_t[t];
-    // Each block owns a contiguous chunk of cell batches (one batch per block
-    // for the apply, several for the smoother so that sB is staged once per
-    // chunk); the remap gives every XCD a contiguous range of cells.
+    if constexpr (EPRO)
+        for (int t = threadIdx.x; t < 2 * N1E * N1; t += blockDim.x)
+            sP[t] = e.P1[t / (N1E * N1)][(t / N1) % N1E][t % N1];
+    // One batch per block, except for the smoother on 64-DoF cells: the grid is
+    // capped there and each block owns a contiguous chunk of batches, so that
+    // its 16-32 KB sB is staged once per chunk.  (A batch loop in the other
+    // kernels would only cost registers: the compiler keeps per-batch values
+    // live across iterations, e.g. 62 -> 128 VGPRs for the 2D Q2 FP32 smoother,
+    // halving its occupancy.)  The remap gives every XCD a contiguous range of cells.
+    constexpr bool CHUNKED = OP == OP_SMOOTH && NC > 27;
     const int nbatch = a.batch_start != nullptr ? a.nbatch : (ncells + CPB - 1) / CPB;
-    const int chunk = OP == OP_SMOOTH ? (nbatch + gridDim.x - 1) / gridDim.x : 1;
+    const int chunk = CHUNKED ? (nbatch + gridDim.x - 1) / gridDim.x : 1;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int bb0 = blk * chunk;
-    const int bb1 = OP == OP_SMOOTH ? min(nbatch, bb0 + chunk) : bb0 + 1;
+    const int bb1 = CHUNKED ? min(nbatch, bb0 + chunk) : bb0 + 1;
 #pragma unroll 1
     for (int bb = bb0; bb < bb1; ++bb) {
         int bstart, bend;
@@ -510,7 +593,8 @@ __global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void cellop_kernel(int cell
             bstart = cell0 + bb * CPB;
             bend = cell0 + ncells;
         }
-        cell_batch<D, P, T, OP, S::WAVES>(L, sB, bb == bb0, bstart, bend, xin, out, b, a, sR);
+        cell_batch<D, P, T, OP, S::WAVES, EMIT, typename EmitParam<T, EMIT>::type>(L, sB, bb == bb0, bstart, bend,
+                                                                                    xin, out, b, a, sR, nullptr, e, sP);
     }
 }
 
@@ -527,9 +611,14 @@ __global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void resid_restrict_kernel(
                                                              const int *__restrict__ perm,
                                                              const int *__restrict__ grp, const T *xin,
                                                              const T *__restrict__ b, T *__restrict__ bc,
-                                                             CellArgs<T> a, KRef<T> Rarg, TransferArgs<T> tr) {
+                                                             CellArgs<T> a, KRef<T> Rarg, TransferArgs<T> tr,
+                                                             ZeroStartArgs<T> zs) {
     using S = Sh<D, P>;
     constexpr int N1 = S::N1, NC = S::NC, CPW = S::CPW, CPB = S::CPB;
+    // coarse DoFs per cell when the zero-start update is formed: h-transfers
+    // are Q1 -> Q1, p-transfers Q(P) -> Q(P-1)
+    constexpr int NCC = P == 1 ? NC : (D == 2 ? P * P : P * P * P);
+    constexpr bool ZPRE = NCC <= 16;   // inverse column in registers
     __shared__ CellLds<D, P, T, S::WAVES> L;
     __shared__ KRef<T> sR;
     __shared__ T sP[2][N1][MAXN1];
@@ -549,107 +638,190 @@ __global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void resid_restrict_kernel(
         bstart = a.batch_start[blk];
         bend = min(bstart + CPB, bstart < a.split ? a.split : n_coarse);
     }
-    cell_batch<D, P, T, OP_RESTRICT, S::WAVES>(L, nullptr, true, bstart, bend, xin, nullptr, b, a, sR, perm);
-    // coarse DoFs of this wave's parents: CPW / nch parents, ncc DoFs each
+    // coarse DoFs of this wave's parents: CPW / nch parents, ncc DoFs each;
+    // lane pp * ncc + jq forms DoF jq of parent pp
     const int ncc = D == 2 ? n1c * n1c : n1c * n1c * n1c;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int npar = CPW / nch;
-    if (lane < npar * ncc) {
-        const int pp = lane / ncc, j = lane % ncc;
-        const int g = (bstart + wave * CPW) / nch + pp;   // group (h) or cell (p) of this parent
-        if (perm != nullptr ? g < n_coarse : g < bend) {
-            const int Kc = perm != nullptr ? grp[g] : g;
-            const int j0 = j % n1c, j1 = (j / n1c) % n1c, j2 = D == 3 ? j / (n1c * n1c) : 0;
-            T acc = 0;
-            for (int o = 0; o < nch; ++o) {
-                const int lc = wave * CPW + pp * nch + o;
+    const bool plane = lane < npar * ncc;
+    const int pp = plane ? lane / ncc : 0, jq = plane ? lane % ncc : 0;
+    const int g = (bstart + wave * CPW) / nch + pp;   // group (h) or cell (p) of this parent
+    const bool pvalid = plane && (perm != nullptr ? g < n_coarse : g < bend);
+    const bool zero_start = zs.z != nullptr;
+    int Kc = 0, zbi = -1;
+    if (pvalid) {
+        Kc = perm != nullptr ? grp[g] : g;
+        if (zero_start) zbi = perm != nullptr ? zs.grp_bnd[g] : zs.bnd_of[g];
+    }
+    T zcol[ZPRE ? NCC : 1];
+    auto hook = [&]() {
+        if constexpr (ZPRE) {
+            if (zero_start && pvalid) {
+                const T *Bt = zbi < 0 ? zs.Bint_t : zs.Bbnd_t + (size_t)zbi * NCC * NCC;
 #pragma unroll
-                for (int i = 0; i < NC; ++i) {
-                    const int i0 = i % N1, i1 = (i / N1) % N1, i2 = D == 3 ? i / (N1 * N1) : 0;
-                    T w = sP[o & 1][i0][j0] * sP[(o >> 1) & 1][i1][j1];
-                    if (D == 3) w *= sP[(o >> 2) & 1][i2][j2];
-                    acc += w * L.sa[lc][i];
-                }
+                for (int j = 0; j < NCC; ++j) zcol[j] = Bt[(size_t)j * NCC + jq];
             }
-            bc[(size_t)Kc * ncc + j] = acc;
+        }
+    };
+    cell_batch<D, P, T, OP_RESTRICT, S::WAVES, EMIT_NONE, int, decltype(hook)>(L, nullptr, true, bstart, bend, xin,
+                                                                               nullptr, b, a, sR, perm, 0, nullptr,
+                                                                               hook);
+    T acc = 0;
+    if (pvalid) {
+        const int j0 = jq % n1c, j1 = (jq / n1c) % n1c, j2 = D == 3 ? jq / (n1c * n1c) : 0;
+        for (int o = 0; o < nch; ++o) {
+            const int lc = wave * CPW + pp * nch + o;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                const int i0 = i % N1, i1 = (i / N1) % N1, i2 = D == 3 ? i / (N1 * N1) : 0;
+                T w = sP[o & 1][i0][j0] * sP[(o >> 1) & 1][i1][j1];
+                if (D == 3) w *= sP[(o >> 2) & 1][i2][j2];
+                acc += w * L.sa[lc][i];
+            }
+        }
+        bc[(size_t)Kc * ncc + jq] = acc;
+    }
+    if (zero_start) {
+        // z_K = omega B_K bc_K (colour 0) or 0 (colour 1), in the order of the
+        // zero-start smoothing kernel; the wave's bc values through its LDS slice
+        T *sz = &L.sb[wave * CPW][0];
+        wave_sync();
+        if (pvalid) sz[lane] = acc;
+        wave_sync();
+        if (pvalid) {
+            T zv = 0;
+            if (Kc < zs.split) {
+                T corr = 0;
+                if constexpr (ZPRE) {
+#pragma unroll
+                    for (int j = 0; j < NCC; ++j) corr += zcol[j] * sz[pp * NCC + j];
+                } else {
+                    const T *Bt = zbi < 0 ? zs.Bint_t : zs.Bbnd_t + (size_t)zbi * NCC * NCC;
+#pragma unroll 9
+                    for (int j = 0; j < NCC; ++j) corr += Bt[(size_t)j * NCC + jq] * sz[pp * NCC + j];
+                }
+                zv = T(0) + zs.omega * corr;
+            }
+            zs.z[(size_t)Kc * NCC + jq] = zv;
         }
     }
 }
 
 template <int D, int P, typename T>
 static int launch_rr(int n_coarse, int nch, int n1c, const int *perm, const int *grp, const T *x, const T *b, T *bc,
-                     const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr, hipStream_t st) {
+                     const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr, hipStream_t st,
+                     const ZeroStartArgs<T> *zsp) {
     using S = Sh<D, P>;
     if (n_coarse <= 0) return 0;
     if (S::CPW % nch != 0) return -1;   // a wave must hold whole child groups
     if (perm == nullptr && (nch != 1 || a.batch_start == nullptr)) return -1;
+    ZeroStartArgs<T> zs{};
+    if (zsp != nullptr) {
+        // the zero-start update is sized for Q1 -> Q1 (h) and Q(P) -> Q(P-1) (p)
+        const bool h = perm != nullptr;
+        if ((h ? (P != 1 || n1c != 2 || zsp->grp_bnd == nullptr) : (P < 2 || n1c != P)) || zsp->z == nullptr ||
+            zsp->bnd_of == nullptr || zsp->Bint_t == nullptr || zsp->split < 0 || zsp->split > n_coarse)
+            return -1;
+        zs = *zsp;
+    }
     const int nb = perm != nullptr ? (int)(((long long)n_coarse * nch + S::CPB - 1) / S::CPB) : a.nbatch;
     hipLaunchKernelGGL((resid_restrict_kernel<D, P, T>), dim3(nb), dim3(64 * S::WAVES), 0, st, n_coarse, nch, n1c, perm, grp,
-                       x, b, bc, a, R, tr);
+                       x, b, bc, a, R, tr, zs);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T>
 int launch_resid_restrict(int d, int p, int n_coarse, int nch, int n1c, const int *perm, const int *grp, const T *x,
                           const T *b, T *bc, const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr,
-                          hipStream_t st) {
+                          hipStream_t st, const ZeroStartArgs<T> *zs) {
     if (n1c < 1 || n1c > p + 1) return -1;
     if (d == 2) {
-        if (p == 1) return launch_rr<2, 1, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
-        if (p == 2) return launch_rr<2, 2, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
-        if (p == 3) return launch_rr<2, 3, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
+        if (p == 1) return launch_rr<2, 1, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
+        if (p == 2) return launch_rr<2, 2, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
+        if (p == 3) return launch_rr<2, 3, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
     } else {
-        if (p == 1) return launch_rr<3, 1, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
-        if (p == 2) return launch_rr<3, 2, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
-        if (p == 3) return launch_rr<3, 3, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st);
+        if (p == 1) return launch_rr<3, 1, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
+        if (p == 2) return launch_rr<3, 2, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
+        if (p == 3) return launch_rr<3, 3, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
     }
     return -1;
 }
 template int launch_resid_restrict<double>(int, int, int, int, int, const int *, const int *, const double *,
                                            const double *,
                                            double *, const CellArgs<double> &, const KRef<double> &,
-                                           const TransferArgs<double> &, hipStream_t);
+                                           const TransferArgs<double> &, hipStream_t, const ZeroStartArgs<double> *);
 template int launch_resid_restrict<float>(int, int, int, int, int, const int *, const int *, const float *,
                                           const float *, float *,
                                           const CellArgs<float> &, const KRef<float> &, const TransferArgs<float> &,
-                                          hipStream_t);
+                                          hipStream_t, const ZeroStartArgs<float> *);
 
 template <int D, int P, typename T>
 static int launch_dp(int op, int cell0, int ncells, const T *x, T *y, const T *b, const CellArgs<T> &a,
-                     const KRef<T> &R, hipStream_t st) {
+                     const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e) {
     if (ncells <= 0) return 0;
     using S = Sh<D, P>;
     int nb = a.batch_start != nullptr ? a.nbatch : (ncells + S::CPB - 1) / S::CPB;
     // the largest cells (64 DoFs) stage a 16-32 KB shared inverse per block: cap
     // the grid and let each block walk several batches
     if (op == OP_SMOOTH && S::NC > 27) nb = std::min(nb, 2048);
+    const dim3 g(nb), bl(64 * S::WAVES);
+    const int kind = e != nullptr ? e->kind : EMIT_NONE;
+    if (op != OP_SMOOTH && kind != EMIT_NONE) return -1;
     if (op == OP_APPLY)
-        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_APPLY>), dim3(nb), dim3(64 * S::WAVES), 0, st, cell0, ncells, x, y, b, a, R);
+        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_APPLY>), g, bl, 0, st, cell0, ncells, x, y, b, a, R, 0);
     else if (op == OP_RESID)
-        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_RESID>), dim3(nb), dim3(64 * S::WAVES), 0, st, cell0, ncells, x, y, b, a, R);
-    else
-        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_SMOOTH>), dim3(nb), dim3(64 * S::WAVES), 0, st, cell0, ncells, x, y, b, a, R);
+        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_RESID>), g, bl, 0, st, cell0, ncells, x, y, b, a, R, 0);
+    else if (kind == EMIT_NONE)
+        hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_SMOOTH>), g, bl, 0, st, cell0, ncells, x, y, b, a, R, 0);
+    else if (kind == EMIT_F64) {
+        if constexpr (std::is_same<T, float>::value) {
+            if (e->z64 == nullptr) return -1;
+            hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_SMOOTH, EMIT_F64>), g, bl, 0, st, cell0, ncells, x, y, b,
+                               a, R, *e);
+        } else {
+            return -1;
+        }
+    } else if (kind == EMIT_H) {
+        if constexpr (P == 1) {
+            if (e->zf == nullptr || e->children == nullptr) return -1;
+            hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_SMOOTH, EMIT_H>), g, bl, 0, st, cell0, ncells, x, y, b, a,
+                               R, *e);
+        } else {
+            return -1;
+        }
+    } else if (kind == EMIT_P) {
+        if constexpr (P <= 2) {
+            if (e->zf == nullptr || e->children == nullptr) return -1;
+            hipLaunchKernelGGL((cellop_kernel<D, P, T, OP_SMOOTH, EMIT_P>), g, bl, 0, st, cell0, ncells, x, y, b, a,
+                               R, *e);
+        } else {
+            return -1;
+        }
+    } else {
+        return -1;
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T>
 int launch_cellop(int d, int p, int op, int cell0, int ncells, const T *x, T *y, const T *b, const CellArgs<T> &a,
-                  const KRef<T> &R, hipStream_t st) {
+                  const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e) {
     if (d == 2) {
-        if (p == 1) return launch_dp<2, 1, T>(op, cell0, ncells, x, y, b, a, R, st);
-        if (p == 2) return launch_dp<2, 2, T>(op, cell0, ncells, x, y, b, a, R, st);
-        if (p == 3) return launch_dp<2, 3, T>(op, cell0, ncells, x, y, b, a, R, st);
+        if (p == 1) return launch_dp<2, 1, T>(op, cell0, ncells, x, y, b, a, R, st, e);
+        if (p == 2) return launch_dp<2, 2, T>(op, cell0, ncells, x, y, b, a, R, st, e);
+        if (p == 3) return launch_dp<2, 3, T>(op, cell0, ncells, x, y, b, a, R, st, e);
     } else {
-        if (p == 1) return launch_dp<3, 1, T>(op, cell0, ncells, x, y, b, a, R, st);
-        if (p == 2) return launch_dp<3, 2, T>(op, cell0, ncells, x, y, b, a, R, st);
-        if (p == 3) return launch_dp<3, 3, T>(op, cell0, ncells, x, y, b, a, R, st);
+        if (p == 1) return launch_dp<3, 1, T>(op, cell0, ncells, x, y, b, a, R, st, e);
+        if (p == 2) return launch_dp<3, 2, T>(op, cell0, ncells, x, y, b, a, R, st, e);
+        if (p == 3) return launch_dp<3, 3, T>(op, cell0, ncells, x, y, b, a, R, st, e);
     }
     return -1;
 }
 template int launch_cellop<double>(int, int, int, int, int, const double *, double *, const double *,
-                                   const CellArgs<double> &, const KRef<double> &, hipStream_t);
+                                   const CellArgs<double> &, const KRef<double> &, hipStream_t,
+                                   const EmitArgs<double> *);
 template int launch_cellop<float>(int, int, int, int, int, const float *, float *, const float *,
-                                  const CellArgs<float> &, const KRef<float> &, hipStream_t);
+                                  const CellArgs<float> &, const KRef<float> &, hipStream_t, const EmitArgs<float> *);
 
 // First colour-0 update of a smoothing step that starts from z = 0: the
 // residual is b itself, so colour-0 cells get z_K = omega B_K b_K (with the

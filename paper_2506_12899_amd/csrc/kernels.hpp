@@ -39,16 +39,45 @@ struct TransferArgs {
     T P1[2][MAXN1][MAXN1];
 };
 
+// Where a colour update also sends the cells' new values (the last update of
+// each colour in the last smoothing step of a level, after which they are
+// final): added through the embedding into the next finer level, h (2^d
+// children per cell, Q1) or p (the same cell one degree up), or copied to FP64.
+enum { EMIT_NONE = 0, EMIT_H = 1, EMIT_P = 2, EMIT_F64 = 3 };
+
+template <typename T>
+struct EmitArgs {
+    int kind;
+    const int *children;      // EMIT_H: n_act * 2^d fine cells (-1: inactive); EMIT_P: n_act fine cells
+    T *zf;                    // EMIT_H / EMIT_P: fine-level vector, zf += P z
+    double *z64;              // EMIT_F64: receives z in FP64
+    T P1[2][MAXN1][MAXN1];    // 1D embedding [child offset][fine node][coarse node]
+};
+
+// First colour-0 update of the coarser level from z = 0, formed by the
+// residual-restriction kernel from the right-hand side it has just computed:
+// z_K = omega B_K bc_K for coarse cells K < split, z_K = 0 for the others.
+template <typename T>
+struct ZeroStartArgs {
+    T *z;                     // coarse-level z (all cells written)
+    const int *bnd_of;        // coarse level: boundary-block index of each cell (-1: interior)
+    const int *grp_bnd;       // h-transfers: bnd_of of the coarse cell of each child group
+    const T *Bint_t, *Bbnd_t; // coarse level: transposed cell inverses
+    int split;                // coarse cells of colour 0
+    T omega;
+};
+
 template <typename T>
 int launch_cellop(int d, int p, int op, int cell0, int ncells, const T *x, T *y, const T *b, const CellArgs<T> &a,
-                  const KRef<T> &R, hipStream_t st);
+                  const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e = nullptr);
 // bc = R (b - A x) for the next coarser level: residual and restriction in one
 // launch (perm: child cells grouped by coarse cell, grp: the coarse cell of
 // each group; both ordered spatially)
+// (zs: also the coarser level's zero-start colour-0 update)
 template <typename T>
 int launch_resid_restrict(int d, int p, int n_coarse, int nch, int n1c, const int *perm, const int *grp, const T *x,
                           const T *b, T *bc, const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr,
-                          hipStream_t st);
+                          hipStream_t st, const ZeroStartArgs<T> *zs = nullptr);
 // first colour-0 update from z = 0; b may be FP64 for an FP32 cycle, bcopy
 // (optional) receives b in the cycle precision
 template <typename T, typename TB>

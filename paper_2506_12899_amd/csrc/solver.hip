@@ -165,8 +165,11 @@ int upload_level(sbm_problem *pb, int l, DevLevel<T> &D) {
             std::vector<int> perm((size_t)Lc.n_act * nch);
             for (int g = 0; g < Lc.n_act; ++g)
                 for (int o = 0; o < nch; ++o) perm[(size_t)g * nch + o] = L.children[(size_t)ord[g] * nch + o];
+            std::vector<int> gbnd(Lc.n_act);
+            for (int g = 0; g < Lc.n_act; ++g) gbnd[g] = Lc.bnd_of[ord[g]];
             if ((rc = upload(pb, &D.rr_perm, perm.data(), perm.size())) ||
-                (rc = upload(pb, &D.rr_grp, ord.data(), ord.size())))
+                (rc = upload(pb, &D.rr_grp, ord.data(), ord.size())) ||
+                (rc = upload(pb, &D.rr_gbnd, gbnd.data(), gbnd.size())))
                 return rc;
         }
         double P1[2][MAXN1][MAXN1];
@@ -221,14 +224,28 @@ int level_apply(sbm_problem *pb, int l, int op, const T *x, T *y, const T *b) {
     return SBM_OK;
 }
 
+// em: the updated cells' values also go there (see EmitArgs)
 template <typename T>
-int colour_update(sbm_problem *pb, int l, int colour, const T *b, T *z) {
+int colour_update(sbm_problem *pb, int l, int colour, const T *b, T *z, const EmitArgs<T> *em = nullptr) {
     auto &D = devlevels<T>(pb)[l];
     int c0 = colour == 0 ? 0 : D.n_col0;
     int nc = colour == 0 ? D.n_col0 : D.n_act - D.n_col0;
     bool learned = pb->learned_on && D.lw != nullptr && l == (int)pb->levels.size() - 1;
-    KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, c0, nc, z, z, b, cell_args(D, learned), D.kref, pb->stream));
+    KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, c0, nc, z, z, b, cell_args(D, learned), D.kref, pb->stream, em));
     return SBM_OK;
+}
+
+// Emission of level l - 1's final z into level l's zf: zf += P z (Sec. 3.2)
+template <typename T>
+EmitArgs<T> prolong_emit(sbm_problem *pb, int l, T *zf) {
+    auto &Df = devlevels<T>(pb)[l];
+    EmitArgs<T> e{};
+    e.kind = pb->levels[l].ratio == 2 ? EMIT_H : EMIT_P;
+    e.children = Df.children;
+    e.zf = zf;
+    e.z64 = nullptr;
+    std::memcpy(e.P1, Df.P1, sizeof(e.P1));
+    return e;
 }
 
 template <typename T>
@@ -242,9 +259,11 @@ int restrict_to(sbm_problem *pb, int l, const T *rf, T *bc) {
     return SBM_OK;
 }
 
-// bc = R (b - A_l z): residual of level l restricted to level l - 1, one launch
+// bc = R (b - A_l z): residual of level l restricted to level l - 1, one
+// launch; with zc also level l - 1's zero-start colour-0 update zc = omega B bc
+// (colour 0) and 0 (colour 1)
 template <typename T>
-int resid_restrict(sbm_problem *pb, int l, const T *z, const T *b, T *bc) {
+int resid_restrict(sbm_problem *pb, int l, const T *z, const T *b, T *bc, T *zc = nullptr) {
     auto &Df = devlevels<T>(pb)[l];
     auto &Dc = devlevels<T>(pb)[l - 1];
     TransferArgs<T> tr;
@@ -254,8 +273,19 @@ int resid_restrict(sbm_problem *pb, int l, const T *z, const T *b, T *bc) {
     CellArgs<T> ca = cell_args(Df, false);
     ca.batch_start = Df.batch_start;
     ca.nbatch = Df.nbatch;
+    ZeroStartArgs<T> zs{};
+    if (zc != nullptr) {
+        zs.z = zc;
+        zs.bnd_of = Dc.bnd_of;
+        zs.grp_bnd = nch == 1 ? nullptr : Df.rr_gbnd;
+        zs.Bint_t = Dc.Bint_t;
+        zs.Bbnd_t = Dc.Bbnd_t;
+        zs.split = Dc.n_col0;
+        zs.omega = Dc.kref.omega;
+    }
     KCHK(launch_resid_restrict<T>(Df.d, Df.p, Dc.n_act, nch, Dc.p + 1, nch == 1 ? nullptr : Df.rr_perm,
-                                  nch == 1 ? nullptr : Df.rr_grp, z, b, bc, ca, Df.kref, tr, pb->stream));
+                                  nch == 1 ? nullptr : Df.rr_grp, z, b, bc, ca, Df.kref, tr, pb->stream,
+                                  zc != nullptr ? &zs : nullptr));
     return SBM_OK;
 }
 
@@ -275,13 +305,19 @@ int prolong_add(sbm_problem *pb, int l, const T *zc, T *zf) {
 // (cells of one colour do not couple), so that update adds zero up to rounding
 // and is skipped.  With omega != 1 or the learned correction it is kept.
 // from_zero: z starts at zero; with b64 (FP32 cycle only) the right-hand side
-// is read in FP64 and its FP32 copy written to b on the way.
+// is read in FP64 and its FP32 copy written to b on the way.  started: that
+// first colour-0 update from zero was already formed (by the finer level's
+// residual-restriction kernel).  em: the last update of each colour also sends
+// the values on (they are final after it when this is the last step).
 template <typename T>
-int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false, const double *b64 = nullptr) {
+int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false, const double *b64 = nullptr,
+              bool started = false, const EmitArgs<T> *em = nullptr) {
     const bool learned_here = pb->learned_on && l == (int)pb->levels.size() - 1;
     const bool skip_repeat = pb->opt.omega == 1.0 && !learned_here;
     int rc;
-    if (from_zero) {
+    if (started) {
+        // nothing: z holds the zero-start colour-0 update
+    } else if (from_zero) {
         auto &D = devlevels<T>(pb)[l];
         const CellArgs<T> ca = cell_args(D, learned_here && D.lw != nullptr);
         if (b64 != nullptr) {
@@ -294,16 +330,24 @@ int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false, 
     } else if ((rc = colour_update<T>(pb, l, 0, b, z))) {
         return rc;
     }
-    if ((rc = colour_update<T>(pb, l, 1, b, z))) return rc;
     if (!skip_repeat && (rc = colour_update<T>(pb, l, 1, b, z))) return rc;
-    return colour_update<T>(pb, l, 0, b, z);
+    if ((rc = colour_update<T>(pb, l, 1, b, z, em))) return rc;
+    return colour_update<T>(pb, l, 0, b, z, em);
 }
 
 // b64 (FP32 cycle at the finest level only): the FP64 right-hand side; b is
 // then the cycle's own FP32 buffer, filled by the first smoothing kernel.
+// started: z already holds the zero-start colour-0 update (formed by the finer
+// level).  em: where the final z also goes; *emitted says whether it went
+// (else the caller moves it itself).  With fused transfers (the default) the
+// restriction forms the coarser level's zero-start update and the coarser
+// level's last smoothing kernels add its final z into this level's z, so
+// neither needs a launch of its own.
 template <typename T>
-int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z, const double *b64 = nullptr) {
+int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z, const double *b64 = nullptr, bool started = false,
+               const EmitArgs<T> *em = nullptr, bool *emitted = nullptr) {
     auto &D = devlevels<T>(pb)[l];
+    if (emitted) *emitted = false;
     if (l == 0) {
         if constexpr (std::is_same<T, float>::value) {
             // a one-level hierarchy: the FP32 copy of the right-hand side first
@@ -314,24 +358,31 @@ int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z, const double *b64 = nul
         KCHK((launch_dense_gemv<double, T>(pb->coarse.n, pb->coarse.Ainv64, b, z, pb->stream)));
         return SBM_OK;
     }
+    const bool fuse = pb->opt.fuse_transfers != 0;
+    const int nu_pre = pb->opt.nu_pre, nu_post = pb->opt.nu_post;
     int rc;
-    if (pb->opt.nu_pre > 0) {
+    if (nu_pre > 0) {
         // z starts at zero: the first colour-0 update needs no operator application
-        if ((rc = ssor_step<T>(pb, l, b, z, true, b64))) return rc;
+        if ((rc = ssor_step<T>(pb, l, b, z, true, b64, started))) return rc;
     } else {
         if constexpr (std::is_same<T, float>::value) {
             if (b64 != nullptr) KCHK(launch_cast_d2f(D.n_act * (long long)D.nc, b64, const_cast<float *>(b), pb->stream));
         }
         KCHK(launch_fill<T>((long long)D.n_act * D.nc, z, T(0), pb->stream));
     }
-    for (int s = 1; s < pb->opt.nu_pre; ++s)
+    for (int s = 1; s < nu_pre; ++s)
         if ((rc = ssor_step<T>(pb, l, b, z))) return rc;
     auto &Dc = devlevels<T>(pb)[l - 1];
-    if ((rc = resid_restrict<T>(pb, l, z, b, Dc.b))) return rc;
-    if ((rc = vcycle_rec<T>(pb, l - 1, Dc.b, Dc.z))) return rc;
-    if ((rc = prolong_add<T>(pb, l, Dc.z, z))) return rc;
-    for (int s = 0; s < pb->opt.nu_post; ++s)
-        if ((rc = ssor_step<T>(pb, l, b, z))) return rc;
+    const bool zs = fuse && nu_pre > 0 && l - 1 > 0;
+    if ((rc = resid_restrict<T>(pb, l, z, b, Dc.b, zs ? Dc.z : nullptr))) return rc;
+    EmitArgs<T> up{};
+    if (fuse) up = prolong_emit<T>(pb, l, z);
+    bool done = false;
+    if ((rc = vcycle_rec<T>(pb, l - 1, Dc.b, Dc.z, nullptr, zs, fuse ? &up : nullptr, &done))) return rc;
+    if (!done && (rc = prolong_add<T>(pb, l, Dc.z, z))) return rc;
+    for (int s = 0; s < nu_post; ++s)
+        if ((rc = ssor_step<T>(pb, l, b, z, false, nullptr, false, s == nu_post - 1 ? em : nullptr))) return rc;
+    if (emitted) *emitted = em != nullptr && nu_post > 0;
     return SBM_OK;
 }
 
@@ -381,6 +432,7 @@ int sbm_default_options(int dim, int p, sbm_options *o) {
     o->coarse_dofs = 2048;
     o->vcycle_fp32 = 0;
     o->allow_singular = 0;
+    o->fuse_transfers = 1;
     o->device = 0;
     o->stream = nullptr;
     return SBM_OK;
@@ -803,9 +855,16 @@ int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, in
         while (j < m && its < max_iter) {
             double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
             if (f32) {
-                // the cycle reads v_j in FP64 and keeps its own FP32 copy
-                if ((rc = vcycle_rec<float>(pb, lf, pb->f32_in, pb->f32_out, vj))) return rc;
-                KCHK(launch_cast_f2d(n, pb->f32_out, zj, s));
+                // the cycle reads v_j in FP64 and keeps its own FP32 copy; its
+                // last smoothing kernels write z_j in FP64
+                EmitArgs<float> e64{};
+                e64.kind = EMIT_F64;
+                e64.z64 = zj;
+                bool done = false;
+                if ((rc = vcycle_rec<float>(pb, lf, pb->f32_in, pb->f32_out, vj, false,
+                                            pb->opt.fuse_transfers ? &e64 : nullptr, &done)))
+                    return rc;
+                if (!done) KCHK(launch_cast_f2d(n, pb->f32_out, zj, s));
             } else {
                 if ((rc = vcycle_rec<double>(pb, lf, vj, zj))) return rc;
             }

@@ -33,7 +33,8 @@ class Options(C.Structure):
     _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("c_F", C.c_double), ("c_G", C.c_double),
                 ("alpha", C.c_double), ("ext", C.c_int), ("omega", C.c_double),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarse_min", C.c_int), ("coarse_dofs", C.c_int),
-                ("vcycle_fp32", C.c_int), ("allow_singular", C.c_int), ("device", C.c_int),
+                ("vcycle_fp32", C.c_int), ("allow_singular", C.c_int), ("fuse_transfers", C.c_int),
+                ("device", C.c_int),
                 ("stream", C.c_void_p)]
 
 

@@ -58,7 +58,9 @@ IDS = [c[0] for c in CASES]
 def pair(request):
     name, geo, n, p, kw = request.param
     print(f"[parity] case {name} n={n} p={p} {kw}", flush=True)
-    return _pair(geo, n, p, **kw)
+    pb, H, dev = _pair(geo, n, p, **kw)
+    pb.case = (geo, n, p, kw)
+    return pb, H, dev
 
 
 def test_apply_all_levels(pair):
@@ -128,6 +130,44 @@ def test_vcycle_is_deterministic(pair):
     assert np.array_equal(a, b)
 
 
+def test_fused_transfers_match_separate_kernels(pair):
+    """The V-cycle with the transfers folded into the smoothing and restriction
+    kernels against the one with separate transfer kernels: same arithmetic."""
+    pb, H, dev = pair
+    from paper_2506_12899_amd.problem import Problem
+    geo, n, p, kw = pb.case
+    pb0 = Problem(geo, n, p, device=0, fuse_transfers=0, **kw)
+    r = workloads.random_vector(H.fine.n_dofs, seed=64)
+    for dt, tol in ((torch.float64, 1e-13), (torch.float32, 1e-6)):
+        a = pb.vcycle(_t(r, dev, dt)).cpu().numpy().astype(np.float64)
+        b = pb0.vcycle(_t(r, dev, dt)).cpu().numpy().astype(np.float64)
+        assert _rel(a, b) <= tol, dt
+
+
+# Smoothing schedules: every branch of the fused V-cycle (repeated colour-1
+# update, several steps, no pre- or post-smoothing) against the oracle
+SCHEDULES = [
+    ("disk_q2_omega", workloads.balls([[0.03, -0.02]], [0.7]), 32, 2, {"omega": 0.9, "coarse_dofs": 0}),
+    ("disk_q1_nu22", workloads.balls([[0.03, -0.02]], [0.7]), 32, 1, {"nu_pre": 2, "nu_post": 2, "coarse_dofs": 0}),
+    ("star_q2_nopre", workloads.star(0.6, 0.15, 5), 32, 2, {"nu_pre": 0, "coarse_dofs": 0}),
+    ("star_q2_nopost", workloads.star(0.6, 0.15, 5), 32, 2, {"nu_post": 0, "coarse_dofs": 0}),
+    ("sphere_q2_nu21", workloads.balls([[0.03, -0.02, 0.01]], [0.75]), 16, 2, {"nu_pre": 2, "coarse_dofs": 0}),
+]
+
+
+@pytest.mark.parametrize("name,geo,n,p,kw", SCHEDULES, ids=[c[0] for c in SCHEDULES])
+def test_vcycle_schedules(name, geo, n, p, kw):
+    print(f"[parity] schedule {name} n={n} p={p} {kw}", flush=True)
+    pb, H, dev = _pair(geo, n, p, **kw)
+    r = workloads.random_vector(H.fine.n_dofs, seed=65)
+    ref = H.vcycle(r)
+    z = pb.vcycle(_t(r, dev)).cpu().numpy()
+    assert _rel(z, ref) <= TOL64
+    kappa = max(np.linalg.cond(L.D).max() for L in H.levels if L.n_act)
+    z32 = pb.vcycle(_t(r, dev, torch.float32)).cpu().numpy().astype(np.float64)
+    assert _rel(z32, ref) <= max(TOL32, 5e-8 * kappa), kappa
+
+
 # Deep hierarchies: h-coarsening continues down to the coarse_min rule
 DEEP_CASES = [
     ("disk_q2_deep", workloads.balls([[0.03, -0.02]], [0.7]), 32, 2),
@@ -154,7 +194,7 @@ def test_vcycle_deep_hierarchy(name, geo, n, p):
 
 
 SOLVE_CASES = [
-    ("disk32_q1", {}), ("disk32_q1", {"vcycle_fp32": 1}),
+    ("disk32_q1", {}), ("disk32_q1", {"vcycle_fp32": 1}), ("disk32_q1", {"vcycle_fp32": 1, "fuse_transfers": 0}),
 ]
 
 
