@@ -1152,6 +1152,92 @@ int launch_dense_gemv(int n, const TA *A, const TX *x, TX *y, hipStream_t st) {
 template int launch_dense_gemv<double, double>(int, const double *, const double *, double *, hipStream_t);
 template int launch_dense_gemv<double, float>(int, const double *, const float *, float *, hipStream_t);
 
+// Coarsest-level solve y = Ainv x with the prolongation into the next level
+// in the same launch: block K computes the rows of coarse cell K (Q1, one wave
+// per row), then adds E y_K into the fine cells of K (h: its 2^d children, p:
+// the same cell in Q2), as the prolongation kernel does.
+template <int D, typename TX, int EMIT>
+__global__ __launch_bounds__(64 * (1 << D)) void coarse_solve_prolong_kernel(int n, const double *__restrict__ A,
+                                                                             const TX *__restrict__ x,
+                                                                             TX *__restrict__ y, EmitArgs<TX> e) {
+    static_assert(EMIT == EMIT_H || EMIT == EMIT_P, "prolongation only");
+    constexpr int NCC = 1 << D;                       // Q1 coarse cell
+    constexpr int N1E = EMIT == EMIT_P ? 3 : 2;       // fine nodes per direction
+    constexpr int NCE = D == 2 ? N1E * N1E : N1E * N1E * N1E;
+    constexpr int NOUT = EMIT == EMIT_H ? NCC * NCE : NCE;
+    __shared__ TX sP[2 * N1E * 2];
+    __shared__ TX sy[NCC];
+    const int K = blockIdx.x, t = threadIdx.x;
+    for (int q = t; q < 2 * N1E * 2; q += blockDim.x) sP[q] = e.P1[q / (N1E * 2)][(q / 2) % N1E][q % 2];
+    // the fine value this thread updates, loaded before the products
+    const int o = EMIT == EMIT_H ? t / NCE : 0, ao = t % NCE;
+    int F = -1;
+    TX zold = 0;
+    if (t < NOUT) {
+        F = EMIT == EMIT_H ? e.children[(size_t)K * NCC + o] : e.children[K];
+        if (F >= 0) zold = e.zf[(size_t)F * NCE + ao];
+    }
+    const int row = K * NCC + (t >> 6);
+    {
+        const int lane = t & 63;
+        const double *a = A + (size_t)row * n;
+        double acc = 0;
+        for (int j0 = lane; j0 < n; j0 += 256) {
+            double av[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + 64 * u;
+                av[u] = j < n ? a[j] : 0.0;
+                xv[u] = j < n ? (double)x[j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += av[u] * xv[u];
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (lane == 0) {
+            y[row] = (TX)acc;
+            sy[t >> 6] = (TX)acc;
+        }
+    }
+    __syncthreads();
+    if (F >= 0) {
+        const int a0 = ao % N1E, a1 = (ao / N1E) % N1E, a2 = D == 3 ? ao / (N1E * N1E) : 0;
+        TX acc = 0;
+#pragma unroll
+        for (int j = 0; j < NCC; ++j) {
+            const int j0 = j & 1, j1 = (j >> 1) & 1, j2 = (j >> 2) & 1;
+            TX w = sP[((o & 1) * N1E + a0) * 2 + j0] * sP[(((o >> 1) & 1) * N1E + a1) * 2 + j1];
+            if (D == 3) w *= sP[(((o >> 2) & 1) * N1E + a2) * 2 + j2];
+            acc += w * sy[j];
+        }
+        e.zf[(size_t)F * NCE + ao] = zold + acc;
+    }
+}
+
+template <typename TX>
+int launch_coarse_solve_prolong(int d, int n, const double *A, const TX *x, TX *y, const EmitArgs<TX> &e,
+                                hipStream_t st) {
+    const int ncc = 1 << d;
+    if (n <= 0) return 0;
+    if (n % ncc != 0 || e.children == nullptr || e.zf == nullptr) return -1;
+    const dim3 g(n / ncc), bl(64 * ncc);
+    if (d == 2 && e.kind == EMIT_H)
+        hipLaunchKernelGGL((coarse_solve_prolong_kernel<2, TX, EMIT_H>), g, bl, 0, st, n, A, x, y, e);
+    else if (d == 2 && e.kind == EMIT_P)
+        hipLaunchKernelGGL((coarse_solve_prolong_kernel<2, TX, EMIT_P>), g, bl, 0, st, n, A, x, y, e);
+    else if (d == 3 && e.kind == EMIT_H)
+        hipLaunchKernelGGL((coarse_solve_prolong_kernel<3, TX, EMIT_H>), g, bl, 0, st, n, A, x, y, e);
+    else if (d == 3 && e.kind == EMIT_P)
+        hipLaunchKernelGGL((coarse_solve_prolong_kernel<3, TX, EMIT_P>), g, bl, 0, st, n, A, x, y, e);
+    else
+        return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template int launch_coarse_solve_prolong<double>(int, int, const double *, const double *, double *,
+                                                 const EmitArgs<double> &, hipStream_t);
+template int launch_coarse_solve_prolong<float>(int, int, const double *, const float *, float *,
+                                                const EmitArgs<float> &, hipStream_t);
+
 // --------------------------------------------------------------------------
 template <typename T>
 __global__ void fill_kernel(long long n, T *x, T v) {

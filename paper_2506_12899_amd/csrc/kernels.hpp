@@ -91,6 +91,11 @@ int launch_restrict(int d, int n_coarse, int n1f, int n1c, int nch, const int *c
                     const TransferArgs<T> &tr, hipStream_t st);
 template <typename TA, typename TX>
 int launch_dense_gemv(int n, const TA *A, const TX *x, TX *y, hipStream_t st);
+// y = A x on a Q1 coarsest level (n = n_cells * 2^d) and e's prolongation of y
+// into the next level (EMIT_H or EMIT_P) in one launch
+template <typename TX>
+int launch_coarse_solve_prolong(int d, int n, const double *A, const TX *x, TX *y, const EmitArgs<TX> &e,
+                                hipStream_t st);
 template <typename T>
 int launch_fill(long long n, T *x, T v, hipStream_t st);
 int launch_cast_d2f(long long n, const double *x, float *y, hipStream_t st);

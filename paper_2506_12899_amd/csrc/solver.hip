@@ -355,7 +355,12 @@ int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z, const double *b64 = nul
         }
         // the coarsest problem is tiny and can be badly conditioned: the FP32
         // cycle also solves it with the FP64 inverse
-        KCHK((launch_dense_gemv<double, T>(pb->coarse.n, pb->coarse.Ainv64, b, z, pb->stream)));
+        if (em != nullptr && (em->kind == EMIT_H || em->kind == EMIT_P) && D.p == 1) {
+            KCHK(launch_coarse_solve_prolong<T>(D.d, pb->coarse.n, pb->coarse.Ainv64, b, z, *em, pb->stream));
+            if (emitted) *emitted = true;
+        } else {
+            KCHK((launch_dense_gemv<double, T>(pb->coarse.n, pb->coarse.Ainv64, b, z, pb->stream)));
+        }
         return SBM_OK;
     }
     const bool fuse = pb->opt.fuse_transfers != 0;
