@@ -107,6 +107,47 @@ def time_apply(pb, torch, fp32, reps=200, warm=20):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
+def time_apply_cold(pb, torch, fp32, reps=20, scrub_bytes=1 << 30):
+    """Median time of one finest-level apply after a 1 GiB write that evicts
+    x, y and the tables from the 256 MB Infinity Cache and the L2s."""
+    dt = torch.float32 if fp32 else torch.float64
+    x = torch.randn(pb.n_dofs, dtype=torch.float64, generator=torch.Generator().manual_seed(1)).to("cuda", dt)
+    y = torch.empty_like(x)
+    scrub = torch.empty(scrub_bytes // 4, dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream()
+    ts = []
+    for r in range(reps + 2):
+        scrub.fill_(float(r))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        pb.apply(x, y)
+        e1.record(s)
+        torch.cuda.synchronize()
+        if r >= 2:
+            ts.append(e0.elapsed_time(e1) / 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def copy_probe(torch, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth: a 1 GiB device-to-device copy (bytes read +
+    written per second), beside the vendor peak."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2 * nbytes / t / 1e9
+
+
 def cpu_baseline(prob, gpu_its, budget_s=60.0):
     """The oracle (plain NumPy/SciPy FP64) on the host: full FGMRES solve to 1e-8."""
     import numpy as np
@@ -206,6 +247,9 @@ def main():
     ta64 = time_apply(pb, torch, False, args.apply_reps)
     ta32 = time_apply(pb, torch, True, args.apply_reps)
     ts32 = time_smooth(pb, torch, True, args.apply_reps)
+    tc64 = time_apply_cold(pb, torch, False)
+    tc32 = time_apply_cold(pb, torch, True)
+    copy_gbs = copy_probe(torch)
     by64, by32 = apply_bytes(pb, False), apply_bytes(pb, True)
     bs32 = smooth_pair_bytes(pb, True) / 2          # per launch (average of the two colours)
     gbs64 = by64 / ta64 / 1e9
@@ -231,6 +275,9 @@ def main():
         "speedup_fp32_vs_fp64": t64 / t32,
         "apply_mdofs_fp64": pb.n_dofs / ta64 / 1e6, "apply_mdofs_fp32": pb.n_dofs / ta32 / 1e6,
         "apply_gbs_fp32": by32 / ta32 / 1e9,
+        "apply_cold_mdofs_fp64": pb.n_dofs / tc64 / 1e6, "apply_cold_mdofs_fp32": pb.n_dofs / tc32 / 1e6,
+        "apply_cold_gbs_fp64": by64 / tc64 / 1e9, "apply_cold_gbs_fp32": by32 / tc32 / 1e9,
+        "hbm_copy_probe_gbs": copy_gbs,
         "setup_s": setup_s,
         "roofline": roof,
         "roofline_apply": roof_apply,
