@@ -612,7 +612,7 @@ __global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void resid_restrict_kernel(
                                                              const int *__restrict__ grp, const T *xin,
                                                              const T *__restrict__ b, T *__restrict__ bc,
                                                              CellArgs<T> a, KRef<T> Rarg, TransferArgs<T> tr,
-                                                             ZeroStartArgs<T> zs) {
+                                                             ZeroStartArgs<T> zs, int c1_only) {
     using S = Sh<D, P>;
     constexpr int N1 = S::N1, NC = S::NC, CPW = S::CPW, CPB = S::CPB;
     // coarse DoFs per cell when the zero-start update is formed: h-transfers
@@ -634,6 +634,16 @@ __global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void resid_restrict_kernel(
     if (perm != nullptr) {
         bstart = blk * CPB;
         bend = n_coarse * nch;
+    } else if (c1_only) {
+        // the colour-0 residual vanishes: colour-1 batches only, and the
+        // colour-0 part of bc (and of the zero-start z) is zero
+        bstart = a.split + blk * CPB;
+        bend = min(bstart + CPB, n_coarse);
+        const long long nz = (long long)a.split * (D == 2 ? n1c * n1c : n1c * n1c * n1c);
+        for (long long t = (long long)blk * blockDim.x + threadIdx.x; t < nz; t += (long long)gridDim.x * blockDim.x) {
+            bc[t] = T(0);
+            if (zs.z != nullptr) zs.z[t] = T(0);
+        }
     } else {
         bstart = a.batch_start[blk];
         bend = min(bstart + CPB, bstart < a.split ? a.split : n_coarse);
@@ -710,11 +720,12 @@ __global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void resid_restrict_kernel(
 template <int D, int P, typename T>
 static int launch_rr(int n_coarse, int nch, int n1c, const int *perm, const int *grp, const T *x, const T *b, T *bc,
                      const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr, hipStream_t st,
-                     const ZeroStartArgs<T> *zsp) {
+                     const ZeroStartArgs<T> *zsp, bool c1_only) {
     using S = Sh<D, P>;
     if (n_coarse <= 0) return 0;
     if (S::CPW % nch != 0) return -1;   // a wave must hold whole child groups
     if (perm == nullptr && (nch != 1 || a.batch_start == nullptr)) return -1;
+    if (c1_only && (perm != nullptr || a.split < 0 || a.split > n_coarse)) return -1;
     ZeroStartArgs<T> zs{};
     if (zsp != nullptr) {
         // the zero-start update is sized for Q1 -> Q1 (h) and Q(P) -> Q(P-1) (p)
@@ -724,36 +735,38 @@ static int launch_rr(int n_coarse, int nch, int n1c, const int *perm, const int 
             return -1;
         zs = *zsp;
     }
-    const int nb = perm != nullptr ? (int)(((long long)n_coarse * nch + S::CPB - 1) / S::CPB) : a.nbatch;
+    int nb = perm != nullptr ? (int)(((long long)n_coarse * nch + S::CPB - 1) / S::CPB) : a.nbatch;
+    if (c1_only) nb = std::max(1, (n_coarse - a.split + S::CPB - 1) / S::CPB);
     hipLaunchKernelGGL((resid_restrict_kernel<D, P, T>), dim3(nb), dim3(64 * S::WAVES), 0, st, n_coarse, nch, n1c, perm, grp,
-                       x, b, bc, a, R, tr, zs);
+                       x, b, bc, a, R, tr, zs, c1_only ? 1 : 0);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T>
 int launch_resid_restrict(int d, int p, int n_coarse, int nch, int n1c, const int *perm, const int *grp, const T *x,
                           const T *b, T *bc, const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr,
-                          hipStream_t st, const ZeroStartArgs<T> *zs) {
+                          hipStream_t st, const ZeroStartArgs<T> *zs, bool c1_only) {
     if (n1c < 1 || n1c > p + 1) return -1;
     if (d == 2) {
-        if (p == 1) return launch_rr<2, 1, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
-        if (p == 2) return launch_rr<2, 2, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
-        if (p == 3) return launch_rr<2, 3, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
+        if (p == 1) return launch_rr<2, 1, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs, c1_only);
+        if (p == 2) return launch_rr<2, 2, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs, c1_only);
+        if (p == 3) return launch_rr<2, 3, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs, c1_only);
     } else {
-        if (p == 1) return launch_rr<3, 1, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
-        if (p == 2) return launch_rr<3, 2, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
-        if (p == 3) return launch_rr<3, 3, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs);
+        if (p == 1) return launch_rr<3, 1, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs, c1_only);
+        if (p == 2) return launch_rr<3, 2, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs, c1_only);
+        if (p == 3) return launch_rr<3, 3, T>(n_coarse, nch, n1c, perm, grp, x, b, bc, a, R, tr, st, zs, c1_only);
     }
     return -1;
 }
 template int launch_resid_restrict<double>(int, int, int, int, int, const int *, const int *, const double *,
                                            const double *,
                                            double *, const CellArgs<double> &, const KRef<double> &,
-                                           const TransferArgs<double> &, hipStream_t, const ZeroStartArgs<double> *);
+                                           const TransferArgs<double> &, hipStream_t, const ZeroStartArgs<double> *,
+                                           bool);
 template int launch_resid_restrict<float>(int, int, int, int, int, const int *, const int *, const float *,
                                           const float *, float *,
                                           const CellArgs<float> &, const KRef<float> &, const TransferArgs<float> &,
-                                          hipStream_t, const ZeroStartArgs<float> *);
+                                          hipStream_t, const ZeroStartArgs<float> *, bool);
 
 template <int D, int P, typename T>
 static int launch_dp(int op, int cell0, int ncells, const T *x, T *y, const T *b, const CellArgs<T> &a,

@@ -73,11 +73,13 @@ int launch_cellop(int d, int p, int op, int cell0, int ncells, const T *x, T *y,
 // bc = R (b - A x) for the next coarser level: residual and restriction in one
 // launch (perm: child cells grouped by coarse cell, grp: the coarse cell of
 // each group; both ordered spatially)
-// (zs: also the coarser level's zero-start colour-0 update)
+// (zs: also the coarser level's zero-start colour-0 update; c1_only, p-transfers:
+// the colour-0 residual is known to vanish, so only colour-1 cells are computed
+// and the colour-0 part of bc and zs->z is set to zero)
 template <typename T>
 int launch_resid_restrict(int d, int p, int n_coarse, int nch, int n1c, const int *perm, const int *grp, const T *x,
                           const T *b, T *bc, const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr,
-                          hipStream_t st, const ZeroStartArgs<T> *zs = nullptr);
+                          hipStream_t st, const ZeroStartArgs<T> *zs = nullptr, bool c1_only = false);
 // first colour-0 update from z = 0; b may be FP64 for an FP32 cycle, bcopy
 // (optional) receives b in the cycle precision
 template <typename T, typename TB>

@@ -283,9 +283,16 @@ int resid_restrict(sbm_problem *pb, int l, const T *z, const T *b, T *bc, T *zc 
         zs.split = Dc.n_col0;
         zs.omega = Dc.kref.omega;
     }
+    // After a smoothing step that ends with an exact colour-0 block solve
+    // (omega = 1, unshifted inverses, no learned correction on this level) the
+    // colour-0 residual is zero up to rounding: a p-transfer then computes only
+    // colour 1 (the cells map one to one, so the colour-0 part of bc is zero).
+    const bool learned_here = pb->learned_on && l == (int)pb->levels.size() - 1 && Df.lw != nullptr;
+    const bool c1_only = nch == 1 && pb->opt.nu_pre > 0 && pb->opt.omega == 1.0 && pb->opt.allow_singular == 0 &&
+                         !learned_here;
     KCHK(launch_resid_restrict<T>(Df.d, Df.p, Dc.n_act, nch, Dc.p + 1, nch == 1 ? nullptr : Df.rr_perm,
                                   nch == 1 ? nullptr : Df.rr_grp, z, b, bc, ca, Df.kref, tr, pb->stream,
-                                  zc != nullptr ? &zs : nullptr));
+                                  zc != nullptr ? &zs : nullptr, c1_only));
     return SBM_OK;
 }
 
