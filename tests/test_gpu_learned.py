@@ -123,6 +123,31 @@ def test_learned_vcycle_matches_oracle(pair):
     assert _rel(z, H.vcycle(r)) <= 1e-10
 
 
+def test_learned_vcycle_omega_one_matches_oracle():
+    """Q2 (omega = 1): with the learned correction the finest colour-0 update is
+    no longer an exact block solve, so its residual must be computed, not
+    taken as zero."""
+    from paper_2506_12899_amd.problem import Problem
+    import ctypes as C
+    from paper_2506_12899_amd import native as Nn
+    dev = _dev()
+    geo = workloads.eight_balls(0)
+    pb = Problem(geo, 8, 2, device=0)
+    H = mg.Hierarchy(oracle_geometry(geo), 3, 8, 2)
+    cells = H.fine.boundary_cells
+    nb, N = len(cells), H.fine.N
+    rng = np.random.default_rng(14)
+    w = rng.uniform(0.5, 1.5, nb)
+    U = rng.standard_normal((nb, N, 4)) * 0.05
+    V = rng.standard_normal((nb, N, 4)) * 0.05
+    P = lambda a: np.ascontiguousarray(a).ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+    Nn.check(Nn.lib().sbm_set_learned_arrays(pb._h, P(w), P(U), P(V)), pb._h)
+    H.learned = (w, U, V, cells)
+    r = workloads.random_vector(H.fine.n_dofs, seed=15)
+    z = pb.vcycle(torch.from_numpy(r).to(dev)).cpu().numpy()
+    assert _rel(z, H.vcycle(r)) <= 1e-10
+
+
 def test_zero_head_inference_reproduces_plain_vcycle(pair):
     pb, H = pair
     dev = _dev()
