@@ -193,8 +193,12 @@ def test_vcycle_deep_hierarchy(name, geo, n, p):
     assert _rel(z32, ref) <= max(TOL32, 5e-8 * kappa), kappa
 
 
+# (with the default coarsest-level size the 32^2 Q1 disk is one level and a
+# direct solve; coarse_dofs = 256 keeps three levels)
 SOLVE_CASES = [
-    ("disk32_q1", {}), ("disk32_q1", {"vcycle_fp32": 1}), ("disk32_q1", {"vcycle_fp32": 1, "fuse_transfers": 0}),
+    ("disk32_q1", {}), ("disk32_q1", {"vcycle_fp32": 1}),
+    ("disk32_q1", {"coarse_dofs": 256}), ("disk32_q1", {"coarse_dofs": 256, "vcycle_fp32": 1}),
+    ("disk32_q1", {"coarse_dofs": 256, "vcycle_fp32": 1, "fuse_transfers": 0}),
 ]
 
 
@@ -216,3 +220,43 @@ def test_solve_true_residual(name, kw):
     # the oracle's own MG-FGMRES reaches the same discrete solution
     xo, its, rel, conv, _ = krylov.fgmres(L.apply, H.vcycle, bo, tol=1e-10)
     assert _rel(xn, xo) <= 1e-5
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_solve_with_restarts(fp32):
+    """FGMRES(4): several restart cycles, each ending with the true residual."""
+    from paper_2506_12899_amd.problem import Problem
+    dev = _gpu()
+    prob = workloads.problem("disk32_q1")
+    print(f"[parity] restarts fp32={fp32}", flush=True)
+    # a small coarsest level, so that the 32^2 Q1 disk keeps a multigrid hierarchy
+    pb = Problem(prob.geometry, prob.n, prob.p, device=0, vcycle_fp32=fp32, coarse_dofs=256)
+    assert pb.n_levels >= 3
+    b = pb.rhs(prob.solution.f, prob.solution.u)
+    x, st = pb.solve(b, tol=1e-8, restart=4, max_iter=200)
+    assert st["converged"] and st["rel_residual"] <= 1e-8 and st["iterations"] > 4
+    H = mg.Hierarchy(oracle_geometry(prob.geometry), prob.dim, prob.n, prob.p)
+    L = H.fine
+    bo = b.cpu().numpy()
+    xn = x.cpu().numpy()
+    assert np.linalg.norm(bo - L.A @ xn) <= 1e-8 * np.linalg.norm(bo) * (1 + 1e-6)
+    xo, _, _, _, _ = krylov.fgmres(L.apply, H.vcycle, bo, tol=1e-10)
+    assert _rel(xn, xo) <= 1e-5
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_solve_one_level_exact_preconditioner(fp32):
+    """One level: the V-cycle is the dense inverse, A z = v lies in the basis
+    already, and the first step ends FGMRES (the Gram-Schmidt second pass and
+    the zero-norm branch are taken)."""
+    from paper_2506_12899_amd.problem import Problem
+    dev = _gpu()
+    geo = workloads.balls([[0.03, -0.02]], [0.7])
+    print(f"[parity] one-level solve fp32={fp32}", flush=True)
+    pb = Problem(geo, 8, 1, device=0, vcycle_fp32=fp32, coarse_dofs=4096)
+    assert pb.n_levels == 1
+    b = torch.from_numpy(workloads.random_vector(pb.n_dofs, seed=66)).to(dev)
+    x, st = pb.solve(b, tol=1e-8)
+    assert st["converged"] and st["rel_residual"] <= 1e-8 and st["iterations"] <= 2
+    H = mg.Hierarchy(oracle_geometry(geo), 2, 8, 1, coarse_dofs=4096)
+    assert np.linalg.norm(b.cpu().numpy() - H.fine.A @ x.cpu().numpy()) <= 1e-8 * np.linalg.norm(b.cpu().numpy())
