@@ -1501,10 +1501,16 @@ __global__ __launch_bounds__(256) void gs_axpy_scale_kernel(long long n, int m, 
     for (int i = 0; i < MB; ++i) hh[i] = i < m ? h[i] : 0.0;
     const long long st = (long long)gridDim.x * blockDim.x;
     for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
+        // all loads of the element first (left to itself the compiler issues
+        // the 32-vector case one load at a time)
+        double vk[MB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) vk[i] = V[(size_t)(i < m ? i : m - 1) * n + k];
+        const double wk = w[k];
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < MB; ++i) s += hh[i] * V[(size_t)(i < m ? i : m - 1) * n + k];
-        v[k] = (w[k] - s) * inv;
+        for (int i = 0; i < MB; ++i) s += hh[i] * vk[i];
+        v[k] = (wk - s) * inv;
     }
 }
 int launch_gs_axpy_scale(long long n, int m, const double *V, const double *h, double inv, const double *w, double *v,
@@ -1522,19 +1528,35 @@ int launch_gs_axpy_scale(long long n, int m, const double *V, const double *h, d
 }
 
 // w += sign * sum_i h[i] V_i
+// (instantiated for a bound MB >= m like the Gram-Schmidt kernels, all loads
+// of an element issued before the products)
+template <int MB>
 __global__ __launch_bounds__(256) void multiaxpy_kernel(long long n, int m, double sign, const double *__restrict__ h,
                                                         const double *__restrict__ V, double *__restrict__ w) {
+    double hh[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) hh[i] = i < m ? h[i] : 0.0;
     long long st = (long long)gridDim.x * blockDim.x;
     for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
+        double vk[MB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) vk[i] = V[(size_t)(i < m ? i : m - 1) * n + k];
         double acc = 0.0;
-        for (int i = 0; i < m; ++i) acc += h[i] * V[(size_t)i * n + k];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) acc += hh[i] * vk[i];
         w[k] += sign * acc;
     }
 }
 int launch_multiaxpy(long long n, int m, double sign, const double *h, const double *V, double *w, hipStream_t st) {
     if (n <= 0 || m <= 0) return 0;
-    int nb = (int)std::min<long long>((n + 255) / 256, 8192);
-    hipLaunchKernelGGL(multiaxpy_kernel, dim3(nb), dim3(256), 0, st, n, m, sign, h, V, w);
+    if (m > GS_MAXV) return -1;
+    const dim3 g((unsigned)std::min<long long>((n + 255) / 256, 8192)), bl(256);
+    switch (gs_bucket(m)) {
+        case 4: hipLaunchKernelGGL(multiaxpy_kernel<4>, g, bl, 0, st, n, m, sign, h, V, w); break;
+        case 8: hipLaunchKernelGGL(multiaxpy_kernel<8>, g, bl, 0, st, n, m, sign, h, V, w); break;
+        case 16: hipLaunchKernelGGL(multiaxpy_kernel<16>, g, bl, 0, st, n, m, sign, h, V, w); break;
+        default: hipLaunchKernelGGL(multiaxpy_kernel<32>, g, bl, 0, st, n, m, sign, h, V, w);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
