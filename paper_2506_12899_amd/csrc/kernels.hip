@@ -195,12 +195,13 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
     // faces) or the shift vector at the face Gauss point (surrogate
     // faces).  Loaded here, consumed after the volume stage.
     constexpr int ITEMS = (NFACE * NF + NC - 1) / NC;
-    // Register budget (measured on the 3D Q2 solve): the boundary-cell inverse
-    // column stays in registers up to 16 entries; the shift-stage loops unroll
-    // fully up to 16 DoFs per cell, partly for 27 (by 3 in FP32, 9 in FP64) and
-    // not for 64, trading the latency of dependent LDS reads against occupancy.
+    // Register budget (measured on the 3D Q2 and Q3 solves): the boundary-cell
+    // inverse column stays in registers up to 16 entries; the shift-stage loops
+    // unroll fully up to 16 DoFs per cell and partly above (27: by 3 in FP32, 9
+    // in FP64; 64: by 8, which beat 1 by 8 % and 16 by 9 % on the 3D Q3 solve),
+    // trading the latency of dependent LDS reads against occupancy.
     constexpr bool PRE_B = NC <= 16;
-    constexpr int SHIFT_UNROLL = NC <= 16 ? NC : (NC <= 27 ? (sizeof(T) == 4 ? 3 : 9) : 1);
+    constexpr int SHIFT_UNROLL = NC <= 16 ? NC : (NC <= 27 ? (sizeof(T) == 4 ? 3 : 9) : 8);
     constexpr int CORR_UNROLL = NC <= 27 ? NC : 8;
     T raw[ITEMS][N1];
     T dqr[ITEMS][D];
