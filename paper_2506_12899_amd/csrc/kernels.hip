@@ -197,11 +197,12 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
     constexpr int ITEMS = (NFACE * NF + NC - 1) / NC;
     // Register budget (measured on the 3D Q2 and Q3 solves): the boundary-cell
     // inverse column stays in registers up to 16 entries; the shift-stage loops
-    // unroll fully up to 16 DoFs per cell and partly above (27: by 3 in FP32, 9
-    // in FP64; 64: by 8, which beat 1 by 8 % and 16 by 9 % on the 3D Q3 solve),
-    // trading the latency of dependent LDS reads against occupancy.
+    // unroll fully up to 16 DoFs per cell, and for 27 in FP32 (1.5 % on the 3D
+    // Q2 solve; FP64 loses 9 % that way and unrolls by 9); 64-DoF cells unroll
+    // by 8 (better than 1 by 8 % and than 16 by 9 % on the 3D Q3 solve): the
+    // latency of dependent LDS reads traded against occupancy.
     constexpr bool PRE_B = NC <= 16;
-    constexpr int SHIFT_UNROLL = NC <= 16 ? NC : (NC <= 27 ? (sizeof(T) == 4 ? 3 : 9) : 8);
+    constexpr int SHIFT_UNROLL = NC <= 16 ? NC : (NC <= 27 ? (sizeof(T) == 4 ? 27 : 9) : 8);
     constexpr int CORR_UNROLL = NC <= 27 ? NC : 8;
     T raw[ITEMS][N1];
     T dqr[ITEMS][D];
