@@ -14,7 +14,7 @@
 //
 // Thread mapping: one thread per DoF, 64 / (p+1)^d cells per wave (a cell
 // never straddles a wave, so the cell's threads exchange LDS data without
-// block barriers), 2 waves per block (4 for 64-DoF cells); cell data staged in
+// block barriers), 2 waves per block, one batch of cells per block; cell data staged in
 // LDS.  The
 // block index is remapped so that each of the 8 XCDs works on a contiguous
 // range of cells (neighbour traces then hit that XCD's L2).
@@ -471,7 +471,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
         T xnew = 0;
         if (live) {
             T corr = 0;
-            if (bi < 0) {
+            if (bi < 0 && NC <= 27) {
 #pragma unroll(CORR_UNROLL)
                 for (int j = 0; j < NC; ++j) corr += sB[j * NC + i] * sa[lc][j];
             } else if (PRE_B) {
@@ -480,7 +480,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
             } else {
                 // large blocks: the column in groups of 16 loads in flight (the
                 // last group is cut at NC)
-                const T *Bt = a.Bbnd_t + (size_t)bi * NC * NC;
+                const T *Bt = (NC > 27 && bi < 0) ? a.Bint_t : a.Bbnd_t + (size_t)bi * NC * NC;
 #pragma unroll 1
                 for (int j0 = 0; j0 < NC; j0 += 16) {
                     T col[16];
@@ -548,8 +548,17 @@ struct EmitParam<T, EMIT_NONE> {
     using type = int;
 };
 
+// Occupancy floor handed to the register allocator (waves per SIMD): the 3D
+// Q2 FP64 colour update fits 168 VGPRs (3 waves) without spilling but is
+// otherwise allocated 170 (2 waves, 10 % slower solve).
+template <int D, int P, typename T, int OP>
+constexpr int cell_min_waves() {
+    return (D == 3 && P == 2 && sizeof(T) == 8 && OP == OP_SMOOTH) ? 3 : 1;
+}
+
 template <int D, int P, typename T, int OP, int EMIT = EMIT_NONE>
-__global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void cellop_kernel(int cell0, int ncells, const T *xin, T *out,
+__global__ __launch_bounds__((64 * Sh<D, P>::WAVES))
+__attribute__((amdgpu_waves_per_eu(cell_min_waves<D, P, T, OP>(), 8))) void cellop_kernel(int cell0, int ncells, const T *xin, T *out,
                                                     const T *__restrict__ b, CellArgs<T> a, KRef<T> Rarg,
                                                     typename EmitParam<T, EMIT>::type e) {
     using S = Sh<D, P>;
@@ -557,7 +566,11 @@ __global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void cellop_kernel(int cell
     constexpr bool EPRO = EMIT == EMIT_H || EMIT == EMIT_P;
     constexpr int N1E = EMIT == EMIT_P ? N1 + 1 : N1;
     __shared__ CellLds<D, P, T, S::WAVES> L;
-    __shared__ T sB[OP == OP_SMOOTH ? NC * NC : 1];  // shared interior-cell inverse
+    // shared interior-cell inverse (up to 27 DoFs per cell; 64-DoF cells read its
+    // columns from memory like the boundary blocks: staging 16-32 KB per block
+    // cost more than it saved)
+    constexpr bool SB = OP == OP_SMOOTH && NC <= 27;
+    __shared__ T sB[SB ? NC * NC : 1];
     __shared__ KRef<T> sR;
     __shared__ T sP[EPRO ? 2 * N1E * N1 : 1];     // embedding for the emission
     // The reference data are indexed per lane; read from the kernel arguments
@@ -568,36 +581,26 @@ __global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void cellop_kernel(int cell
         unsigned *dst = reinterpret_cast<unsigned *>(&sR);
         for (int t = threadIdx.x; t < (int)(sizeof(KRef<T>) / 4); t += blockDim.x) dst[t] = src[t];
     }
-    if (OP == OP_SMOOTH)
+    if (SB)
         for (int t = threadIdx.x; t < NC * NC; t += blockDim.x) sB[t] = a.Bint_t[t];
     if constexpr (EPRO)
         for (int t = threadIdx.x; t < 2 * N1E * N1; t += blockDim.x)
             sP[t] = e.P1[t / (N1E * N1)][(t / N1) % N1E][t % N1];
-    // One batch per block, except for the smoother on 64-DoF cells: the grid is
-    // capped there and each block owns a contiguous chunk of batches, so that
-    // its 16-32 KB sB is staged once per chunk.  (A batch loop in the other
-    // kernels would only cost registers: the compiler keeps per-batch values
-    // live across iterations, e.g. 62 -> 128 VGPRs for the 2D Q2 FP32 smoother,
-    // halving its occupancy.)  The remap gives every XCD a contiguous range of cells.
-    constexpr bool CHUNKED = OP == OP_SMOOTH && NC > 27;
-    const int nbatch = a.batch_start != nullptr ? a.nbatch : (ncells + CPB - 1) / CPB;
-    const int chunk = CHUNKED ? (nbatch + gridDim.x - 1) / gridDim.x : 1;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int bb0 = blk * chunk;
-    const int bb1 = CHUNKED ? min(nbatch, bb0 + chunk) : bb0 + 1;
-#pragma unroll 1
-    for (int bb = bb0; bb < bb1; ++bb) {
-        int bstart, bend;
-        if (a.batch_start != nullptr) {
-            bstart = a.batch_start[bb];
-            bend = min(bstart + CPB, bstart < a.split ? a.split : cell0 + ncells);
-        } else {
-            bstart = cell0 + bb * CPB;
-            bend = cell0 + ncells;
-        }
-        cell_batch<D, P, T, OP, S::WAVES, EMIT, typename EmitParam<T, EMIT>::type>(L, sB, bb == bb0, bstart, bend,
-                                                                                    xin, out, b, a, sR, nullptr, e, sP);
+    // One batch per block.  (A batch loop would cost registers even when it runs
+    // once: the compiler keeps per-batch values live across iterations, e.g.
+    // 62 -> 128 VGPRs for the 2D Q2 FP32 smoother, halving its occupancy.)  The
+    // remap gives every XCD a contiguous range of cells.
+    const int bb = xcd_remap(blockIdx.x, gridDim.x);
+    int bstart, bend;
+    if (a.batch_start != nullptr) {
+        bstart = a.batch_start[bb];
+        bend = min(bstart + CPB, bstart < a.split ? a.split : cell0 + ncells);
+    } else {
+        bstart = cell0 + bb * CPB;
+        bend = cell0 + ncells;
     }
+    cell_batch<D, P, T, OP, S::WAVES, EMIT, typename EmitParam<T, EMIT>::type>(L, sB, true, bstart, bend, xin, out, b,
+                                                                                a, sR, nullptr, e, sP);
 }
 
 // Residual and restriction in one launch (Sec. 3.2: the restriction is the
@@ -608,8 +611,11 @@ __global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void cellop_kernel(int cell
 //    in LDS and the wave forms bc = sum_o E_o^T r_o.
 //  p-transfer (same cells, perm = nullptr): batches follow the whole-level
 //    batch table and every cell restricts its own residual.
+// (occupancy floor as for the cell kernels: the 3D Q2 FP64 form fits 3 waves
+// per SIMD without spilling but is otherwise allocated 169 VGPRs, 2 waves)
 template <int D, int P, typename T>
-__global__ __launch_bounds__((64 * Sh<D, P>::WAVES)) void resid_restrict_kernel(int n_coarse, int nch, int n1c,
+__global__ __launch_bounds__((64 * Sh<D, P>::WAVES))
+__attribute__((amdgpu_waves_per_eu((D == 3 && P == 2 && sizeof(T) == 8) ? 3 : 1, 8))) void resid_restrict_kernel(int n_coarse, int nch, int n1c,
                                                              const int *__restrict__ perm,
                                                              const int *__restrict__ grp, const T *xin,
                                                              const T *__restrict__ b, T *__restrict__ bc,
@@ -776,9 +782,6 @@ static int launch_dp(int op, int cell0, int ncells, const T *x, T *y, const T *b
     if (ncells <= 0) return 0;
     using S = Sh<D, P>;
     int nb = a.batch_start != nullptr ? a.nbatch : (ncells + S::CPB - 1) / S::CPB;
-    // the largest cells (64 DoFs) stage a 16-32 KB shared inverse per block: cap
-    // the grid and let each block walk several batches
-    if (op == OP_SMOOTH && S::NC > 27) nb = std::min(nb, 2048);
     const dim3 g(nb), bl(64 * S::WAVES);
     const int kind = e != nullptr ? e->kind : EMIT_NONE;
     if (op != OP_SMOOTH && kind != EMIT_NONE) return -1;

@@ -24,9 +24,8 @@ struct CellArgs {
 };
 
 // waves per block of the cell kernels for cells of nc DoFs (measured: two
-// waves, except four for 64-DoF cells, whose blocks stage a large shared
-// inverse)
-constexpr int cell_waves(int nc) { return nc >= 64 ? 4 : 2; }
+// waves; four and one were slower on the 2D Q2, 3D Q2 and 3D Q3 solves)
+constexpr int cell_waves(int) { return 2; }
 
 // cells per block of the cell kernels (cell_waves waves, 64 / (p+1)^d cells per wave)
 inline int cells_per_block(int d, int p) {
