@@ -549,11 +549,12 @@ struct EmitParam<T, EMIT_NONE> {
 };
 
 // Occupancy floor handed to the register allocator (waves per SIMD): the 3D
-// Q2 FP64 colour update fits 168 VGPRs (3 waves) without spilling but is
-// otherwise allocated 170 (2 waves, 10 % slower solve).
+// Q2 colour updates are otherwise allocated just above a boundary, 170 VGPRs
+// in FP64 and 97 in FP32, and fit 168 (3 waves) and 96 (5 waves); measured on
+// the 3D Q2 solve: FP64 10 % and FP32 4 % faster.
 template <int D, int P, typename T, int OP>
 constexpr int cell_min_waves() {
-    return (D == 3 && P == 2 && sizeof(T) == 8 && OP == OP_SMOOTH) ? 3 : 1;
+    return (D == 3 && P == 2 && OP == OP_SMOOTH) ? (sizeof(T) == 8 ? 3 : 5) : 1;
 }
 
 template <int D, int P, typename T, int OP, int EMIT = EMIT_NONE>
