@@ -287,23 +287,29 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
     if (live) {
 #pragma unroll
         for (int q = 0; q < ITEMS; ++q) {
-            int it = i + q * NC;
-            if (it >= NFACE * NF) break;
-            int f = it / NF, j = it % NF, s = f & 1;
-            int nb = snb[lc][f];
-            T va = 0, vb = 0;
-            if (nb >= 0) {
-                const T *gN = R.g[s == 1 ? 0 : 1];
-                T t = s == 1 ? raw[q][0] : raw[q][P];
-                T dn = 0;
+            const int it = i + q * NC;
+            if (it < NFACE * NF) {
+                int f = it / NF, j = it % NF, s = f & 1;
+                int nb = snb[lc][f];
+                T va = 0, vb = 0;
+                if (nb >= 0) {
+                    const T *gN = R.g[s == 1 ? 0 : 1];
+                    // the trace node picked by 0/1 weights (exact), not by a
+                    // select: the compiler turns a select of two elements into
+                    // a dynamic index, and raw then lives in scratch memory
+                    T t = 0, dn = 0;
 #pragma unroll
-                for (int m = 0; m < N1; ++m) dn += gN[m] * raw[q][m];
-                T sg = s == 1 ? T(1) : T(-1);
-                va = T(-0.5) * sg * dn - R.sigF * t;
-                vb = T(0.5) * t;
+                    for (int m = 0; m < N1; ++m) {
+                        t += T(m == (s == 1 ? 0 : P)) * raw[q][m];
+                        dn += gN[m] * raw[q][m];
+                    }
+                    T sg = s == 1 ? T(1) : T(-1);
+                    va = T(-0.5) * sg * dn - R.sigF * t;
+                    vb = T(0.5) * t;
+                }
+                fa[lc][f][j] = va;
+                fb[lc][f][j] = vb;
             }
-            fa[lc][f][j] = va;
-            fb[lc][f][j] = vb;
         }
     }
     wave_sync();
@@ -552,14 +558,15 @@ struct EmitParam<T, EMIT_NONE> {
 // Q2 colour updates are otherwise allocated just above a boundary, 170 VGPRs
 // in FP64 and 97 in FP32, and fit 168 (3 waves) and 96 (5 waves); measured on
 // the 3D Q2 solve: FP64 10 % and FP32 4 % faster.
-template <int D, int P, typename T, int OP>
+// (The p-prolongation form, which would spill, keeps the default.)
+template <int D, int P, typename T, int OP, int EMIT>
 constexpr int cell_min_waves() {
-    return (D == 3 && P == 2 && OP == OP_SMOOTH) ? (sizeof(T) == 8 ? 3 : 5) : 1;
+    return (D == 3 && P == 2 && OP == OP_SMOOTH && EMIT != EMIT_P) ? (sizeof(T) == 8 ? 3 : 5) : 1;
 }
 
 template <int D, int P, typename T, int OP, int EMIT = EMIT_NONE>
 __global__ __launch_bounds__((64 * Sh<D, P>::WAVES))
-__attribute__((amdgpu_waves_per_eu(cell_min_waves<D, P, T, OP>(), 8))) void cellop_kernel(int cell0, int ncells, const T *xin, T *out,
+__attribute__((amdgpu_waves_per_eu(cell_min_waves<D, P, T, OP, EMIT>(), 8))) void cellop_kernel(int cell0, int ncells, const T *xin, T *out,
                                                     const T *__restrict__ b, CellArgs<T> a, KRef<T> Rarg,
                                                     typename EmitParam<T, EMIT>::type e) {
     using S = Sh<D, P>;
