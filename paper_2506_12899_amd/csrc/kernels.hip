@@ -127,15 +127,46 @@ struct NoHook {
     __device__ void operator()() const {}
 };
 
+// Block-wide copy of a small table (W 32-bit words, NT threads) into LDS in
+// two halves: load() issues all of this thread's loads, store() writes them,
+// so that the kernel's other first loads go out in between.  (A plain copy
+// loop waits for each load before its LDS write: one memory round trip per
+// iteration, ahead of everything else.)
+template <int W, int NT>
+struct Stager {
+    static constexpr int PER = (W + NT - 1) / NT;
+    unsigned v[PER];
+    __device__ __forceinline__ void load(const void *src) {
+        const unsigned *s = reinterpret_cast<const unsigned *>(src);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int t = (int)threadIdx.x + k * NT;
+            v[k] = t < W ? s[t] : 0u;
+        }
+    }
+    __device__ __forceinline__ void store(void *dst) const {
+        unsigned *d = reinterpret_cast<unsigned *>(dst);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int t = (int)threadIdx.x + k * NT;
+            if (t < W) d[t] = v[k];
+        }
+    }
+};
+
 // EMIT (OP_SMOOTH only): see EmitArgs; e is an EmitArgs<T> unless EMIT_NONE,
 // sP the LDS copy of the fine-by-coarse 1D embedding [2][N1E][N1].  hook()
 // runs once the cell data have arrived, before the neighbour loads: a caller
 // issues loads there whose addresses depend on loads it issued before the batch.
-template <int D, int P, typename T, int OP, int NW, int EMIT = EMIT_NONE, typename EA = int, typename Hook = NoHook>
+// stage(): the block's LDS staging writes (sR, sB, ...), called once the cell
+// data loads are issued and before the barrier that guards those tables.
+template <int D, int P, typename T, int OP, int NW, int EMIT = EMIT_NONE, typename EA = int, typename Hook = NoHook,
+          typename Stage = NoHook>
 __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB, bool first, int bstart, int bend,
                                            const T *xin, T *out, const T *__restrict__ b, const CellArgs<T> &a,
                                            const KRef<T> &R, const int *__restrict__ perm = nullptr,
-                                           const EA &e = EA(), const T *sP = nullptr, Hook hook = Hook()) {
+                                           const EA &e = EA(), const T *sP = nullptr, Hook hook = Hook(),
+                                           Stage stage = Stage()) {
     using S = Sh<D, P>;
     static_assert(EMIT == EMIT_NONE || OP == OP_SMOOTH, "only the smoother sends values on");
     static_assert(EMIT != EMIT_H || P == 1, "h-transfers are between Q1 levels");
@@ -158,11 +189,12 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
     const bool live = slot && slotpos < bend && cell >= 0;
     wave_sync();  // the previous batch is done with this wave's LDS slices
 
-    T bval = 0;
-    int bi = -1;
+    // all of the cell's loads first, then the LDS writes that need them
+    T bval = 0, xv = 0;
+    int bi = -1, nbv = 0;
     if (live) {
-        su[lc][i] = xin[(size_t)cell * NC + i];
-        if (i < NFACE) snb[lc][i] = a.nbr[(size_t)cell * NFACE + i];
+        xv = xin[(size_t)cell * NC + i];
+        if (i < NFACE) nbv = a.nbr[(size_t)cell * NFACE + i];
         if (OP != OP_APPLY) bval = b[(size_t)cell * NC + i];
         if (OP == OP_SMOOTH) bi = a.bnd_of[cell];
     }
@@ -176,6 +208,11 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
     T ezf[EPRO ? NOUT : 1];
     if constexpr (EPRO) {
         if (live) efc = EMIT == EMIT_H ? e.children[(size_t)cell * NC + i] : e.children[cell];
+    }
+    stage();
+    if (live) {
+        su[lc][i] = xv;
+        if (i < NFACE) snb[lc][i] = nbv;
     }
     wave_sync();
     if (first) __syncthreads();   // R and sB staged
@@ -582,18 +619,27 @@ __attribute__((amdgpu_waves_per_eu(cell_min_waves<D, P, T, OP, EMIT>(), 8))) voi
     __shared__ KRef<T> sR;
     __shared__ T sP[EPRO ? 2 * N1E * N1 : 1];     // embedding for the emission
     // The reference data are indexed per lane; read from the kernel arguments
-    // every access would be a memory round trip on the critical path.
-    {
-        static_assert(sizeof(KRef<T>) % 4 == 0, "KRef is copied as 32-bit words");
-        const unsigned *src = reinterpret_cast<const unsigned *>(&Rarg);
-        unsigned *dst = reinterpret_cast<unsigned *>(&sR);
-        for (int t = threadIdx.x; t < (int)(sizeof(KRef<T>) / 4); t += blockDim.x) dst[t] = src[t];
+    // every access would be a memory round trip on the critical path.  Their
+    // loads go out first; the LDS writes follow the cell data loads.
+    static_assert(sizeof(KRef<T>) % 4 == 0, "KRef is copied as 32-bit words");
+    constexpr int NT = 64 * S::WAVES;
+    Stager<(int)(sizeof(KRef<T>) / 4), NT> kst;
+    kst.load(&Rarg);
+    Stager<SB ? (int)(NC * NC * sizeof(T) / 4) : 1, NT> bst;
+    if constexpr (SB) bst.load(a.Bint_t);
+    static_assert(!EPRO || 2 * N1E * N1 <= NT, "one embedding entry per thread");
+    T pv = 0;
+    if constexpr (EPRO) {
+        const int t = threadIdx.x;
+        if (t < 2 * N1E * N1) pv = e.P1[t / (N1E * N1)][(t / N1) % N1E][t % N1];
     }
-    if (SB)
-        for (int t = threadIdx.x; t < NC * NC; t += blockDim.x) sB[t] = a.Bint_t[t];
-    if constexpr (EPRO)
-        for (int t = threadIdx.x; t < 2 * N1E * N1; t += blockDim.x)
-            sP[t] = e.P1[t / (N1E * N1)][(t / N1) % N1E][t % N1];
+    auto stage = [&]() {
+        kst.store(&sR);
+        if constexpr (SB) bst.store(sB);
+        if constexpr (EPRO) {
+            if ((int)threadIdx.x < 2 * N1E * N1) sP[threadIdx.x] = pv;
+        }
+    };
     // One batch per block.  (A batch loop would cost registers even when it runs
     // once: the compiler keeps per-batch values live across iterations, e.g.
     // 62 -> 128 VGPRs for the 2D Q2 FP32 smoother, halving its occupancy.)  The
@@ -607,8 +653,8 @@ __attribute__((amdgpu_waves_per_eu(cell_min_waves<D, P, T, OP, EMIT>(), 8))) voi
         bstart = cell0 + bb * CPB;
         bend = cell0 + ncells;
     }
-    cell_batch<D, P, T, OP, S::WAVES, EMIT, typename EmitParam<T, EMIT>::type>(L, sB, true, bstart, bend, xin, out, b,
-                                                                                a, sR, nullptr, e, sP);
+    cell_batch<D, P, T, OP, S::WAVES, EMIT, typename EmitParam<T, EMIT>::type, NoHook, decltype(stage)>(
+        L, sB, true, bstart, bend, xin, out, b, a, sR, nullptr, e, sP, NoHook(), stage);
 }
 
 // Residual and restriction in one launch (Sec. 3.2: the restriction is the
@@ -638,13 +684,21 @@ __attribute__((amdgpu_waves_per_eu((D == 3 && P == 2 && sizeof(T) == 8) ? 3 : 1,
     __shared__ CellLds<D, P, T, S::WAVES> L;
     __shared__ KRef<T> sR;
     __shared__ T sP[2][N1][MAXN1];
+    // staging loads first, their LDS writes after the batch's cell data loads
+    constexpr int NT = 64 * S::WAVES;
+    Stager<(int)(sizeof(KRef<T>) / 4), NT> kst;
+    kst.load(&Rarg);
+    static_assert(2 * N1 * MAXN1 <= NT, "one embedding entry per thread");
+    T pv = 0;
     {
-        const unsigned *src = reinterpret_cast<const unsigned *>(&Rarg);
-        unsigned *dst = reinterpret_cast<unsigned *>(&sR);
-        for (int t = threadIdx.x; t < (int)(sizeof(KRef<T>) / 4); t += blockDim.x) dst[t] = src[t];
-        for (int t = threadIdx.x; t < 2 * N1 * MAXN1; t += blockDim.x)
-            sP[t / (N1 * MAXN1)][(t / MAXN1) % N1][t % MAXN1] = tr.P1[t / (N1 * MAXN1)][(t / MAXN1) % N1][t % MAXN1];
+        const int t = threadIdx.x;
+        if (t < 2 * N1 * MAXN1) pv = tr.P1[t / (N1 * MAXN1)][(t / MAXN1) % N1][t % MAXN1];
     }
+    auto stage = [&]() {
+        kst.store(&sR);
+        const int t = threadIdx.x;
+        if (t < 2 * N1 * MAXN1) sP[t / (N1 * MAXN1)][(t / MAXN1) % N1][t % MAXN1] = pv;
+    };
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     int bstart, bend;
     if (perm != nullptr) {
@@ -689,9 +743,8 @@ __attribute__((amdgpu_waves_per_eu((D == 3 && P == 2 && sizeof(T) == 8) ? 3 : 1,
             }
         }
     };
-    cell_batch<D, P, T, OP_RESTRICT, S::WAVES, EMIT_NONE, int, decltype(hook)>(L, nullptr, true, bstart, bend, xin,
-                                                                               nullptr, b, a, sR, perm, 0, nullptr,
-                                                                               hook);
+    cell_batch<D, P, T, OP_RESTRICT, S::WAVES, EMIT_NONE, int, decltype(hook), decltype(stage)>(
+        L, nullptr, true, bstart, bend, xin, nullptr, b, a, sR, perm, 0, nullptr, hook, stage);
     T acc = 0;
     if (pvalid) {
         const int j0 = jq % n1c, j1 = (jq / n1c) % n1c, j2 = D == 3 ? jq / (n1c * n1c) : 0;
