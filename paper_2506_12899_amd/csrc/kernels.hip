@@ -251,11 +251,14 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
             if (it < NFACE * NF) {
                 int f = it / NF, j = it % NF, k = f >> 1;
                 int nb = snb[lc][f];
-                if (nb >= 0) {
-                    const T *un = xin + (size_t)nb * NC;
+                // the line is loaded on every face (a surrogate face reads the
+                // cell's own, unused): with the two loads on exclusive branches
+                // the allocator shared their registers and made the shift
+                // loads wait for all the line loads
+                const T *un = xin + (size_t)(nb >= 0 ? nb : cell) * NC;
 #pragma unroll
-                    for (int m = 0; m < N1; ++m) raw[q][m] = un[compose<D, P>(k, m, j)];
-                } else {
+                for (int m = 0; m < N1; ++m) raw[q][m] = un[compose<D, P>(k, m, j)];
+                if (nb < 0) {
                     const T *dq = a.shift + ((size_t)(-nb - 1) * NF + j) * D;
 #pragma unroll
                     for (int c = 0; c < D; ++c) dqr[q][c] = dq[c];
