@@ -911,24 +911,38 @@ template int launch_cellop<float>(int, int, int, int, int, const float *, float 
 // per DoF; replaces clearing z plus a full colour-0 update.
 template <int D, int P, typename T, typename TB>
 __device__ __forceinline__ void smooth_zero_dof(long long t, int split, const TB *__restrict__ b, T *__restrict__ z,
-                                                const CellArgs<T> &a, T omega) {
+                                                const CellArgs<T> &a, T omega, T *__restrict__ bcopy) {
     constexpr int NC = Sh<D, P>::NC;
     const int cell = (int)(t / NC), i = (int)(t % NC);
+    // the first loads together (block index, the cell's right-hand side), the
+    // inverse column, whose address needs the block index, after them
+    const bool c0 = cell < split;
+    const int bi = a.bnd_of[cell];   // (read for every cell: no branch, no wait)
+    const TB *bc = b + (size_t)cell * NC;
+    // up to 16 values per cell: all loaded up front (unconditionally: every
+    // cell's values are valid memory, and a guarded load would be a branch
+    // with its own wait); larger cells stream them with the inverse column
+    // (held in registers they would spill)
+    constexpr bool PRE = NC <= 16;
+    T bv[PRE ? NC : 1];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) bv[j] = (T)bc[j];
+    }
+    if (bcopy != nullptr) bcopy[t] = (T)b[t];
     T out = 0;
-    if (cell < split) {
-        const TB *bc = b + (size_t)cell * NC;
-        const int bi = a.bnd_of[cell];
+    if (c0) {
         const T *Bt = bi < 0 ? a.Bint_t : a.Bbnd_t + (size_t)bi * NC * NC;
         T corr = 0;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) corr += Bt[(size_t)j * NC + i] * (T)bc[j];
+        for (int j = 0; j < NC; ++j) corr += Bt[(size_t)j * NC + i] * (PRE ? bv[PRE ? j : 0] : (T)bc[j]);
         if (a.lw != nullptr && bi >= 0) {
             const T *U = a.lU + (size_t)bi * NC * 4;
             const T *V = a.lV + (size_t)bi * NC * 4;
             T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
 #pragma unroll 8
             for (int j = 0; j < NC; ++j) {
-                T r = (T)bc[j];
+                T r = PRE ? bv[PRE ? j : 0] : (T)bc[j];
                 v0 += V[j * 4 + 0] * r;
                 v1 += V[j * 4 + 1] * r;
                 v2 += V[j * 4 + 2] * r;
@@ -950,8 +964,7 @@ __global__ __launch_bounds__(256) void smooth_zero_kernel(int n_act, int split, 
                                                           T omega) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)n_act * Sh<D, P>::NC) return;
-    if (bcopy != nullptr) bcopy[t] = (T)b[t];
-    smooth_zero_dof<D, P, T, TB>(t, split, b, z, a, omega);
+    smooth_zero_dof<D, P, T, TB>(t, split, b, z, a, omega, bcopy);
 }
 
 template <int D, int P, typename T, typename TB>
@@ -1075,19 +1088,23 @@ __global__ __launch_bounds__(256) void prolong_fixed_kernel(int n_fine, const in
     constexpr int NCF = D == 2 ? N1F * N1F : N1F * N1F * N1F;
     constexpr int NCC = D == 2 ? N1C * N1C : N1C * N1C * N1C;
     __shared__ T sP[2][N1F][N1C];
-    for (int t = threadIdx.x; t < 2 * N1F * N1C; t += blockDim.x)
-        sP[t / (N1F * N1C)][(t / N1C) % N1F][t % N1C] = tr.P1[t / (N1F * N1C)][(t / N1C) % N1F][t % N1C];
+    // every load first (the embedding entry of this thread, the parent, its
+    // values, the old fine value), then the LDS write and the barrier
+    static_assert(2 * N1F * N1C <= 256, "one embedding entry per thread");
+    const int tp = threadIdx.x;
+    const T pv = tp < 2 * N1F * N1C ? tr.P1[tp / (N1F * N1C)][(tp / N1C) % N1F][tp % N1C] : T(0);
     const long long gid0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = gid0 < (long long)n_fine * NCF;
     const long long gid = live ? gid0 : 0;
     const int K = (int)(gid / NCF), i = (int)(gid % NCF);
+    const T zold = zf[(size_t)K * NCF + i];
     const int pc = parent[K];
     const int o = childpos[K];
     T src[NCC];
     const T *zp = zc + (size_t)(pc < 0 ? 0 : pc) * NCC;
 #pragma unroll
     for (int j = 0; j < NCC; ++j) src[j] = pc < 0 ? T(0) : zp[j];
-    const T zold = zf[(size_t)K * NCF + i];
+    if (tp < 2 * N1F * N1C) sP[tp / (N1F * N1C)][(tp / N1C) % N1F][tp % N1C] = pv;
     __syncthreads();
     const int i0 = i % N1F, i1 = (i / N1F) % N1F, i2 = D == 3 ? i / (N1F * N1F) : 0;
     T acc = 0;
@@ -1200,17 +1217,18 @@ __device__ __forceinline__ void gemv_row(int n, int row, const TA *__restrict__ 
     const int lane = threadIdx.x & 63;
     const TA *a = A + (size_t)row * n;
     TA acc = 0;
-    // lane sum over j = lane, lane + 64, ... in that order; four loads in flight
-    for (int j0 = lane; j0 < n; j0 += 256) {
-        TA av[4], xv[4];
+    // lane sum over j = lane, lane + 64, ... in that order; 16 loads in flight
+    // (loads at clamped indices, out-of-range products dropped after)
+    for (int j0 = lane; j0 < n; j0 += 64 * 16) {
+        TA av[16], xv[16];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int j = j0 + 64 * u;
-            av[u] = j < n ? a[j] : TA(0);
-            xv[u] = j < n ? (TA)x[j] : TA(0);
+        for (int u = 0; u < 16; ++u) {
+            const int j = min(j0 + 64 * u, n - 1);
+            av[u] = a[j];
+            xv[u] = (TA)x[j];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc += av[u] * xv[u];
+        for (int u = 0; u < 16; ++u) acc += j0 + 64 * u < n ? av[u] * xv[u] : TA(0);
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if (lane == 0) y[row] = (TX)acc;
@@ -1250,31 +1268,35 @@ __global__ __launch_bounds__(64 * (1 << D)) void coarse_solve_prolong_kernel(int
     __shared__ TX sP[2 * N1E * 2];
     __shared__ TX sy[NCC];
     const int K = blockIdx.x, t = threadIdx.x;
-    for (int q = t; q < 2 * N1E * 2; q += blockDim.x) sP[q] = e.P1[q / (N1E * 2)][(q / 2) % N1E][q % 2];
-    // the fine value this thread updates, loaded before the products
+    const TX pv = t < 2 * N1E * 2 ? e.P1[t / (N1E * 2)][(t / 2) % N1E][t % 2] : TX(0);
+    // the fine cell this thread updates (its old value is loaded once the
+    // first group of row loads is out)
     const int o = EMIT == EMIT_H ? t / NCE : 0, ao = t % NCE;
     int F = -1;
     TX zold = 0;
-    if (t < NOUT) {
-        F = EMIT == EMIT_H ? e.children[(size_t)K * NCC + o] : e.children[K];
-        if (F >= 0) zold = e.zf[(size_t)F * NCE + ao];
-    }
+    if (t < NOUT) F = EMIT == EMIT_H ? e.children[(size_t)K * NCC + o] : e.children[K];
     const int row = K * NCC + (t >> 6);
     {
+        // a lane's share of the row in groups of 32 loads in flight (a row of
+        // up to 2048 DoFs is one group); loads at clamped indices,
+        // out-of-range products dropped after (a guarded load is a branch
+        // with its own wait)
         const int lane = t & 63;
         const double *a = A + (size_t)row * n;
         double acc = 0;
-        for (int j0 = lane; j0 < n; j0 += 256) {
-            double av[4], xv[4];
+        for (int j0 = lane; j0 < n; j0 += 64 * 32) {
+            double av[32], xv[32];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = j0 + 64 * u;
-                av[u] = j < n ? a[j] : 0.0;
-                xv[u] = j < n ? (double)x[j] : 0.0;
+            for (int u = 0; u < 32; ++u) {
+                const int j = min(j0 + 64 * u, n - 1);
+                av[u] = a[j];
+                xv[u] = (double)x[j];
             }
+            if (j0 == lane && F >= 0) zold = e.zf[(size_t)F * NCE + ao];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc += av[u] * xv[u];
+            for (int u = 0; u < 32; ++u) acc += j0 + 64 * u < n ? av[u] * xv[u] : 0.0;
         }
+        if (t < 2 * N1E * 2) sP[t] = pv;
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         if (lane == 0) {
             y[row] = (TX)acc;
