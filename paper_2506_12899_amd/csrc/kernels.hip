@@ -731,11 +731,11 @@ __attribute__((amdgpu_waves_per_eu((D == 3 && P == 2 && sizeof(T) == 8) ? 3 : 1,
     const int g = (bstart + wave * CPW) / nch + pp;   // group (h) or cell (p) of this parent
     const bool pvalid = plane && (perm != nullptr ? g < n_coarse : g < bend);
     const bool zero_start = zs.z != nullptr;
-    int Kc = 0, zbi = -1;
-    if (pvalid) {
-        Kc = perm != nullptr ? grp[g] : g;
-        if (zero_start) zbi = perm != nullptr ? zs.grp_bnd[g] : zs.bnd_of[g];
-    }
+    // read unconditionally (at a clamped group): a guarded load is sunk by the
+    // compiler to its use at the end, one more dependent round trip there
+    const int gc = pvalid ? g : 0;
+    const int Kc = perm != nullptr ? grp[gc] : gc;
+    const int zbi = zero_start ? (perm != nullptr ? zs.grp_bnd[gc] : zs.bnd_of[gc]) : -1;
     T zcol[ZPRE ? NCC : 1];
     auto hook = [&]() {
         if constexpr (ZPRE) {
