@@ -222,7 +222,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
 #pragma unroll
             for (int k = 0; k < NOUT; ++k) {
                 const int ao = EMIT == EMIT_H ? k : i + k * NC;
-                ezf[k] = ao < NCE ? e.zf[(size_t)efc * NCE + ao] : T(0);
+                ezf[k] = e.zf[(size_t)efc * NCE + (ao < NCE ? ao : NCE - 1)];   // (clamped, not guarded)
             }
         }
     }
@@ -531,7 +531,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
                 for (int j0 = 0; j0 < NC; j0 += 16) {
                     T col[16];
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) col[j] = j0 + j < NC ? Bt[(size_t)(j0 + j) * NC + i] : T(0);
+                    for (int j = 0; j < 16; ++j) col[j] = Bt[(size_t)min(j0 + j, NC - 1) * NC + i];   // (clamped)
 #pragma unroll
                     for (int j = 0; j < 16; ++j)
                         if (j0 + j < NC) corr += col[j] * sa[lc][j0 + j];
@@ -1433,17 +1433,27 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ partial,
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
             const int b = lane + 64 * u;
-            t[r][u] = i < nv && b < nblk ? partial[(size_t)b * nv + i] : 0.0;
+            // (loaded at a clamped index and weighted by 0 or 1: a guarded
+            // load, or a select the compiler turns into one, is a branch with
+            // its own wait; the clamped duplicates are finite partial sums)
+            const double pv = partial[(size_t)min(b, nblk - 1) * nv + min(i, nv - 1)];
+            t[r][u] = pv * (i < nv && b < nblk ? 1.0 : 0.0);
         }
+    }
+    // all sums before the first store (a store between the groups of loads
+    // kept the compiler from issuing them together)
+    double v[PER_WAVE];
+#pragma unroll
+    for (int r = 0; r < PER_WAVE; ++r) {
+        v[r] = 0.0;
+#pragma unroll
+        for (int u = 0; u < PER_LANE; ++u) v[r] += t[r][u];
+        v[r] = wave_sum(v[r]);
     }
 #pragma unroll
     for (int r = 0; r < PER_WAVE; ++r) {
         const int i = wave + NW * r;
-        double v = 0.0;
-#pragma unroll
-        for (int u = 0; u < PER_LANE; ++u) v += t[r][u];
-        v = wave_sum(v);
-        if (lane == 0 && i < nv) dst[i] = v;
+        if (lane == 0 && i < nv) dst[i] = v[r];
     }
 }
 
@@ -1589,7 +1599,10 @@ __global__ __launch_bounds__(256) void gs_axpy_scale_kernel(long long n, int m, 
                                                             const double *__restrict__ w, double *__restrict__ v) {
     double hh[MB];
 #pragma unroll
-    for (int i = 0; i < MB; ++i) hh[i] = i < m ? h[i] : 0.0;
+    for (int i = 0; i < MB; ++i) {
+        const double hv = h[i < m ? i : m - 1];   // (clamped, not guarded)
+        hh[i] = i < m ? hv : 0.0;
+    }
     const long long st = (long long)gridDim.x * blockDim.x;
     for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
         // all loads of the element first (left to itself the compiler issues
@@ -1626,7 +1639,10 @@ __global__ __launch_bounds__(256) void multiaxpy_kernel(long long n, int m, doub
                                                         const double *__restrict__ V, double *__restrict__ w) {
     double hh[MB];
 #pragma unroll
-    for (int i = 0; i < MB; ++i) hh[i] = i < m ? h[i] : 0.0;
+    for (int i = 0; i < MB; ++i) {
+        const double hv = h[i < m ? i : m - 1];   // (clamped, not guarded)
+        hh[i] = i < m ? hv : 0.0;
+    }
     long long st = (long long)gridDim.x * blockDim.x;
     for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
         double vk[MB];
