@@ -113,16 +113,6 @@ struct CellLds {
     int snb[CPB][NFACE];
 };
 
-// One batch of cells [bstart, bend), at most NW * CPW of them: wave w takes the
-// cells bstart + w * CPW + (0 .. CPW-1), one thread per DoF.  R and sB (the
-// transposed interior-cell inverse, OP_SMOOTH) are block-shared LDS copies;
-// with first (uniform over the block) a block barrier precedes their first
-// read, so that their staging overlaps the batch's cell-data loads.
-//
-// Every global load is issued as early as its address is known, so that a
-// batch costs three dependent memory round trips (cell data; neighbour traces,
-// shift vectors and the boundary-cell inverse; the store) rather than one per
-// stage: small levels are bound by this latency.
 struct NoHook {
     __device__ void operator()() const {}
 };
@@ -158,11 +148,21 @@ struct Stager {
 // sP the LDS copy of the fine-by-coarse 1D embedding [2][N1E][N1].  hook()
 // runs once the cell data have arrived, before the neighbour loads: a caller
 // issues loads there whose addresses depend on loads it issued before the batch.
+// One batch of cells [bstart, bend), at most NW * CPW of them: wave w takes the
+// cells bstart + w * CPW + (0 .. CPW-1), one thread per DoF.  R and sB (the
+// transposed interior-cell inverse, OP_SMOOTH) are block-shared LDS copies,
+// written by stage() and read after a block barrier, so that their staging
+// overlaps the batch's cell-data loads.
+//
+// Every global load is issued as early as its address is known, so that a
+// batch costs three dependent memory round trips (cell data; neighbour traces,
+// shift vectors and the boundary-cell inverse; the store) rather than one per
+// stage: small levels are bound by this latency.
 // stage(): the block's LDS staging writes (sR, sB, ...), called once the cell
 // data loads are issued and before the barrier that guards those tables.
 template <int D, int P, typename T, int OP, int NW, int EMIT = EMIT_NONE, typename EA = int, typename Hook = NoHook,
           typename Stage = NoHook>
-__device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB, bool first, int bstart, int bend,
+__device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB, int bstart, int bend,
                                            const T *xin, T *out, const T *__restrict__ b, const CellArgs<T> &a,
                                            const KRef<T> &R, const int *__restrict__ perm = nullptr,
                                            const EA &e = EA(), const T *sP = nullptr, Hook hook = Hook(),
@@ -215,7 +215,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
         if (i < NFACE) snb[lc][i] = nbv;
     }
     wave_sync();
-    if (first) __syncthreads();   // R and sB staged
+    __syncthreads();   // R, sB and the embedding staged
     hook();
     if constexpr (EPRO) {
         if (efc >= 0) {
@@ -657,7 +657,7 @@ __attribute__((amdgpu_waves_per_eu(cell_min_waves<D, P, T, OP, EMIT>(), 8))) voi
         bend = cell0 + ncells;
     }
     cell_batch<D, P, T, OP, S::WAVES, EMIT, typename EmitParam<T, EMIT>::type, NoHook, decltype(stage)>(
-        L, sB, true, bstart, bend, xin, out, b, a, sR, nullptr, e, sP, NoHook(), stage);
+        L, sB, bstart, bend, xin, out, b, a, sR, nullptr, e, sP, NoHook(), stage);
 }
 
 // Residual and restriction in one launch (Sec. 3.2: the restriction is the
@@ -747,7 +747,7 @@ __attribute__((amdgpu_waves_per_eu((D == 3 && P == 2 && sizeof(T) == 8) ? 3 : 1,
         }
     };
     cell_batch<D, P, T, OP_RESTRICT, S::WAVES, EMIT_NONE, int, decltype(hook), decltype(stage)>(
-        L, nullptr, true, bstart, bend, xin, nullptr, b, a, sR, perm, 0, nullptr, hook, stage);
+        L, nullptr, bstart, bend, xin, nullptr, b, a, sR, perm, 0, nullptr, hook, stage);
     T acc = 0;
     if (pvalid) {
         const int j0 = jq % n1c, j1 = (jq / n1c) % n1c, j2 = D == 3 ? jq / (n1c * n1c) : 0;
