@@ -471,7 +471,7 @@ def test_newton_closest_point_matches_exact_sphere():
     assert np.allclose(ls.closest(X), SPHERE.closest(X), atol=1e-13)
 
 
-def test_active_set_sizes_match_survey_table():
+def test_active_set_sizes_disk32():
     """Centre rule cell counts of the 2D workloads (cheap enough to recount)."""
     L = dg.Level(DISK.__class__([[0, 0]], [0.7]), 2, 32, 1, build_matrix=False)
     assert (L.n_act, L.n_surr, len(L.boundary_cells)) == (392, 88, 60)
