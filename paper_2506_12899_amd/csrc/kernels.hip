@@ -599,9 +599,14 @@ struct EmitParam<T, EMIT_NONE> {
 // in FP64 and 97 in FP32, and fit 168 (3 waves) and 96 (5 waves); measured on
 // the 3D Q2 solve: FP64 10 % and FP32 4 % faster.
 // (The p-prolongation form, which would spill, keeps the default.)
+// The 3D Q3 FP32 kernels ask for 5: the colour update then fits 76 VGPRs (6
+// waves) instead of the 120 it is given by default, with no spill (3D Q3 FP32
+// solve 8 % faster).  The FP64 forms would fit 96 only by spilling, which was
+// 1.5 % faster but doubled the apply's HBM traffic, so they keep 4 waves.
 template <int D, int P, typename T, int OP, int EMIT>
 constexpr int cell_min_waves() {
-    return (D == 3 && P == 2 && OP == OP_SMOOTH && EMIT != EMIT_P) ? (sizeof(T) == 8 ? 3 : 5) : 1;
+    return (D == 3 && P == 2 && OP == OP_SMOOTH && EMIT != EMIT_P) ? (sizeof(T) == 8 ? 3 : 5)
+         : (D == 3 && P == 3 && sizeof(T) == 4) ? 5 : 1;
 }
 
 template <int D, int P, typename T, int OP, int EMIT = EMIT_NONE>
@@ -669,10 +674,11 @@ __attribute__((amdgpu_waves_per_eu(cell_min_waves<D, P, T, OP, EMIT>(), 8))) voi
 //  p-transfer (same cells, perm = nullptr): batches follow the whole-level
 //    batch table and every cell restricts its own residual.
 // (occupancy floor as for the cell kernels: the 3D Q2 FP64 form fits 3 waves
-// per SIMD without spilling but is otherwise allocated 169 VGPRs, 2 waves)
+// per SIMD without spilling but is otherwise allocated 169 VGPRs, 2 waves; the
+// 3D Q3 FP32 form fits 78 VGPRs, 6 waves, instead of 122)
 template <int D, int P, typename T>
 __global__ __launch_bounds__((64 * Sh<D, P>::WAVES))
-__attribute__((amdgpu_waves_per_eu((D == 3 && P == 2 && sizeof(T) == 8) ? 3 : 1, 8))) void resid_restrict_kernel(int n_coarse, int nch, int n1c,
+__attribute__((amdgpu_waves_per_eu((D == 3 && P == 2 && sizeof(T) == 8) ? 3 : (D == 3 && P == 3 && sizeof(T) == 4) ? 5 : 1, 8))) void resid_restrict_kernel(int n_coarse, int nch, int n1c,
                                                              const int *__restrict__ perm,
                                                              const int *__restrict__ grp, const T *xin,
                                                              const T *__restrict__ b, T *__restrict__ bc,
