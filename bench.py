@@ -254,7 +254,10 @@ def main():
     bs32 = smooth_pair_bytes(pb, True) / 2          # per launch (average of the two colours)
     gbs64 = by64 / ta64 / 1e9
     gbs_s = bs32 / ts32 / 1e9
-    # dominant kernel of the timed (FP32 V-cycle) solve: the finest-level colour update
+    # dominant kernel of the timed (FP32 V-cycle) solve: the finest-level colour update,
+    # the largest share of the solve's kernel time of any kernel on one level (about
+    # 16 % on the 2D Q2 star with its FP64-writing form); on the coarser levels the
+    # same kernel is bound by launch latency, not by bandwidth
     roof = {"bound": "hbm", "kernel": "cellop_kernel<OP_SMOOTH> (finest-level colour update, FP32)",
             "achieved": gbs_s, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs_s / HBM_PEAK_GBS,
             "traffic": counter_traffic(prob.name, "smooth_fp32"), "bytes_per_launch": bs32,
