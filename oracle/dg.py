@@ -241,6 +241,46 @@ class Level:
     def apply(self, x):
         return self.A @ x
 
+    def _cell_blocks(self, K, X, V, Bf):
+        """Diagonal block D_K and the neighbour part sum_F B_{K,nb} x_nb of cell
+        K's rows, from the same element blocks as `assemble` (Sec. 2.2):
+        volume, the SIPG blocks of each interior face (K is the minus side,
+        index 0, when its neighbour lies at the higher coordinate), and the
+        Nitsche-SBM blocks of its surrogate faces."""
+        D = V.copy()
+        off = np.zeros(self.N)
+        for k in range(self.d):
+            B = Bf[k]
+            for s in (0, 1):
+                nb = self.nbr[K, 2 * k + s]
+                if nb >= 0:
+                    me = 0 if s == 1 else 1
+                    D += B[me][me]
+                    if X is not None:
+                        off += B[me][1 - me] @ X[nb]
+        faces = np.nonzero(self.surr_cell == K)[0]
+        if len(faces):
+            D += self.surrogate_blocks(faces).sum(axis=0)
+        return D, off
+
+    def cell_apply(self, cells, x):
+        """(A x)_K for the given active cells, one cell at a time without the
+        global matrix (for sampled checks at sizes where A is too large)."""
+        X = np.asarray(x, dtype=np.float64).reshape(self.n_act, self.N)
+        out = np.zeros((len(cells), self.N))
+        V, Bf = self.volume_block(), [self.interior_face_blocks(k) for k in range(self.d)]
+        for a, K in enumerate(cells):
+            D, off = self._cell_blocks(int(K), X, V, Bf)
+            out[a] = D @ X[K] + off
+        return out
+
+    def cell_diag_blocks(self, cells):
+        """D_K for the given active cells (the blocks the smoother inverts)."""
+        if len(cells) == 0:
+            return np.zeros((0, self.N, self.N))
+        V, Bf = self.volume_block(), [self.interior_face_blocks(k) for k in range(self.d)]
+        return np.stack([self._cell_blocks(int(K), None, V, Bf)[0] for K in cells])
+
     # ---------------------------------------------------------------- data
     def rhs(self, f, g):
         """Right-hand side of the DG-SBM system (Sec. 2.2):

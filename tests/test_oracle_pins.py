@@ -491,3 +491,17 @@ def test_level_shapes():
     assert H.levels[1].n_dofs > 2048 >= H.levels[0].n_dofs
     H = mg.Hierarchy(disk, 2, 32, 1, coarse_dofs=0)
     assert [(L.n, L.p) for L in H.levels] == [(4, 1), (8, 1), (16, 1), (32, 1)]
+
+
+@pytest.mark.parametrize("geo,d,n,p,ext", [(DISK, 2, 16, 2, 1), (DISK, 2, 12, 3, 0), (SPHERE, 3, 8, 2, 1)])
+def test_cell_apply_matches_assembled_rows(geo, d, n, p, ext):
+    """The per-cell operator (used for sampled checks at full size) gives the
+    assembled matrix's rows and diagonal blocks, boundary cells included."""
+    L = dg.Level(geo, d, n, p, ext=ext)
+    x = np.random.default_rng(3).standard_normal(L.n_dofs)
+    cells = np.arange(L.n_act)
+    assert len(L.boundary_cells) > 0
+    y = L.cell_apply(cells, x).ravel()
+    Ax = L.A @ x
+    assert np.abs(y - Ax).max() <= 1e-13 * np.abs(Ax).max()
+    assert np.abs(L.cell_diag_blocks(cells) - L.D).max() <= 1e-13 * np.abs(L.D).max()
