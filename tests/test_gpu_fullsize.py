@@ -5,8 +5,10 @@ The oracle cannot assemble the 3D Q3 operators at these sizes, so the
 finest-level apply and colour updates are checked on sampled cells against the
 oracle's per-cell operator (random interior and boundary cells and both ends
 of each colour); the set-up is checked whole (active cells exactly, shifts to
-rounding); and on the 2D star, whose matrix the oracle does assemble, the
-solve's true residual is recomputed with it.
+rounding); the finest transfer and the first h-transfer are checked on
+sampled coarse and fine cells with rows of the oracle's embedding; and on the
+2D star, whose hierarchy the oracle does assemble, the V-cycle is compared
+entry by entry and the solve's true residual is recomputed with its matrix.
 
 Tolerances as in the small-size parity tests: FP64 1e-10 and FP32 1e-5
 relative over the sampled entries.
@@ -131,3 +133,89 @@ def test_star512_solve_true_residual_with_oracle_matrix():
         rel = np.linalg.norm(bo - L.A @ xn) / np.linalg.norm(bo)
         print(f"[fullsize] star512_q2 fp32={fp32}: {st['iterations']} its, oracle rel {rel:.2e}", flush=True)
         assert rel <= 1e-8 * (1 + 1e-6)
+
+
+_LEVELS = {}
+
+
+def _coarser(prob, n, p):
+    key = (prob.name, n, p)
+    if key not in _LEVELS:
+        _LEVELS[key] = dg.Level(oracle_geometry(prob.geometry), prob.dim, n, p, build_matrix=False)
+    return _LEVELS[key]
+
+
+def _embedding(Lc, Lf, fine_cells):
+    """Rows of the oracle's coarse-to-fine embedding for the given fine cells
+    (row a * Nf + i: fine DoF i of fine_cells[a]), built by the oracle's own
+    routine on a level holding only those cells."""
+    from types import SimpleNamespace
+    sub = SimpleNamespace(d=Lf.d, p=Lf.p, n=Lf.n, N=Lf.N, n_act=len(fine_cells), cells=Lf.cells[fine_cells],
+                          n_dofs=len(fine_cells) * Lf.N)
+    return mg.Hierarchy._prolongation(Lc, sub)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_transfers_sampled(full, fp32):
+    """Restriction bc = P^T r on sampled coarse cells and prolongation
+    zf + P zc on sampled fine cells, for the finest transfer and the first
+    h-transfer (Sec. 3.2: P embeds the coarse space, R = P^T)."""
+    name, prob, pb, L = full
+    pb.set_vcycle_fp32(fp32)
+    nl = pb.n_levels
+    info = [pb.level_info(l) for l in range(nl)]
+    lh = next(l for l in range(nl - 1, 0, -1) if info[l]["n"] == 2 * info[l - 1]["n"])
+    for l in sorted({nl - 1, lh}, reverse=True):
+        Lf = L if l == nl - 1 else _coarser(prob, info[l]["n"], info[l]["p"])
+        Lc = _coarser(prob, info[l - 1]["n"], info[l - 1]["p"])
+        rng = np.random.default_rng(20 + l)
+        # prolongation on sampled fine cells
+        zc = _round(rng.standard_normal(Lc.n_dofs), fp32)
+        zf0 = _round(rng.standard_normal(Lf.n_dofs), fp32)
+        zf = _dev(zf0, fp32)
+        pb.prolong_add(l, _dev(zc, fp32), zf)
+        fc = _sample(Lf, rng)
+        ref = zf0.reshape(Lf.n_act, Lf.N)[fc].ravel() + _embedding(Lc, Lf, fc) @ zc
+        err_p = _rel(_host(zf, Lf)[fc].ravel(), ref)
+        # restriction on sampled coarse cells: every fine child of each
+        cc = _sample(Lc, rng)
+        ratio = Lf.n // Lc.n
+        offs = np.array(np.meshgrid(*[np.arange(ratio)] * prob.dim, indexing="ij")).reshape(prob.dim, -1).T
+        mi = (Lc.cells[cc][:, None, :] * ratio + offs[None]).reshape(-1, prob.dim)
+        kids = Lf.cell_of[Lf.lin_index(mi)]
+        kids = np.unique(kids[kids >= 0])
+        r = _round(rng.standard_normal(Lf.n_dofs), fp32)
+        bc = torch.zeros(Lc.n_dofs, dtype=torch.float32 if fp32 else torch.float64, device="cuda")
+        pb.restrict(l, _dev(r, fp32), bc)
+        Pk = _embedding(Lc, Lf, kids)
+        cols = (cc[:, None] * Lc.N + np.arange(Lc.N)[None]).ravel()
+        ref_r = Pk[:, cols].T @ r.reshape(Lf.n_act, Lf.N)[kids].ravel()
+        err_r = _rel(_host(bc, Lc)[cc].ravel(), ref_r)
+        print(f"[fullsize] {name} transfer l={l} ({info[l]['n']},{info[l]['p']})->({info[l-1]['n']},{info[l-1]['p']}) "
+              f"fp32={fp32}: prolong rel {err_p:.2e}, restrict rel {err_r:.2e} ({len(cc)} coarse cells)", flush=True)
+        assert err_p <= (TOL32 if fp32 else TOL64)
+        assert err_r <= (TOL32 if fp32 else TOL64)
+
+
+def test_star512_vcycle_full_size():
+    """The benchmark's V-cycle (FP64 and FP32, transfers fused as timed) on the
+    full 512^2 Q2 star against the oracle's V-cycle, every entry."""
+    from paper_2506_12899_amd.problem import Problem
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    prob = workloads.problem("star512_q2")
+    print("[fullsize] star512_q2 V-cycle: oracle hierarchy", flush=True)
+    H = mg.Hierarchy(oracle_geometry(prob.geometry), prob.dim, prob.n, prob.p)
+    pb = Problem(prob.geometry, prob.n, prob.p, device=0)
+    assert pb.n_levels == len(H.levels)
+    r = np.random.default_rng(61).standard_normal(H.fine.n_dofs)
+    ref = H.vcycle(r)
+    z = pb.vcycle(_dev(r, 0)).cpu().numpy()
+    pb.set_vcycle_fp32(1)
+    z32 = pb.vcycle(_dev(r, 1)).double().cpu().numpy()
+    # the FP32 bar as in the small-size tests: max(1e-5, 5e-8 kappa_max)
+    kappa = max(np.linalg.cond(L.D).max() for L in H.levels if L.n_act)
+    e64, e32 = _rel(z, ref), _rel(z32, ref)
+    print(f"[fullsize] star512_q2 V-cycle: fp64 rel {e64:.2e}, fp32 rel {e32:.2e} (kappa_max {kappa:.1e})", flush=True)
+    assert e64 <= TOL64
+    assert e32 <= max(TOL32, 5e-8 * kappa)
