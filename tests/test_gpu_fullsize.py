@@ -18,6 +18,7 @@ import pytest
 import torch
 
 from oracle import dg, mg
+from oracle import mlp as omlp
 from paper_2506_12899_amd import workloads
 from tests.oracle_geom import oracle_geometry
 
@@ -61,7 +62,7 @@ def full(request):
     print(f"[fullsize] {name}", flush=True)
     prob = workloads.problem(name)
     pb = Problem(prob.geometry, prob.n, prob.p, device=0)
-    L = dg.Level(oracle_geometry(prob.geometry), prob.dim, prob.n, prob.p, build_matrix=False)
+    L = _coarser(prob, prob.n, prob.p)
     yield name, prob, pb, L
     del pb
 
@@ -219,3 +220,71 @@ def test_star512_vcycle_full_size():
     print(f"[fullsize] star512_q2 V-cycle: fp64 rel {e64:.2e}, fp32 rel {e32:.2e} (kappa_max {kappa:.1e})", flush=True)
     assert e64 <= TOL64
     assert e32 <= max(TOL32, 5e-8 * kappa)
+
+
+def test_learned_correction_full_size():
+    """The learned boundary-cell correction on the 128^3 Q3 eight-ball union:
+    features of every boundary cell against the oracle's, and sampled colour
+    updates z_K + omega w_K (B_K + U_K V_K^T) r_K (FP64 and FP32) with given
+    per-cell w, U, V."""
+    import ctypes as C
+    from paper_2506_12899_amd import native as Nn
+    from paper_2506_12899_amd.learned import boundary_info
+    from paper_2506_12899_amd.problem import Problem
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    prob = workloads.problem("balls128_q3")
+    print("[fullsize] balls128_q3 learned", flush=True)
+    pb = Problem(prob.geometry, prob.n, prob.p, device=0)
+    L = _coarser(prob, prob.n, prob.p)
+    cells, F = boundary_info(pb)
+    assert np.array_equal(cells, L.boundary_cells)
+    d, nf = prob.dim, (L.p + 1) ** (prob.dim - 1)
+    sh = np.zeros((len(cells), 2 * d, nf, d))
+    mask = np.zeros((len(cells), 2 * d))
+    nrm = np.zeros((len(cells), 2 * d, d))
+    pos = -np.ones(L.n_act, dtype=np.int64)
+    pos[cells] = np.arange(len(cells))
+    phi = oracle_geometry(prob.geometry).phi
+    i, face = pos[L.surr_cell], 2 * L.surr_k + L.surr_s
+    sh[i, face] = L.shifts
+    mask[i, face] = 1
+    sgn = -np.sign(phi(L.face_points.reshape(-1, d))).reshape(L.n_surr, nf)
+    ln = np.linalg.norm(L.shifts, axis=2)
+    unit = np.where(ln[..., None] > 0, sgn[..., None] * L.shifts / np.where(ln > 0, ln, 1)[..., None], 0)
+    nrm[i, face] = unit.mean(axis=1)
+    err_f = np.abs(F - omlp.boundary_features(sh, mask, nrm, L.h)).max()
+    print(f"[fullsize] balls128_q3 features: {len(cells)} cells, max diff {err_f:.1e}", flush=True)
+    # the shifts agree to 1e-12 (physical units); the features divide them by
+    # h = 1/64 and the unit normals by |d|, which can be a small fraction of h
+    assert err_f <= 1e-9
+    rng = np.random.default_rng(17)
+    nb, N = len(cells), L.N
+    w = rng.uniform(0.5, 1.5, nb)
+    U = rng.standard_normal((nb, N, 4)) * 0.01
+    V = rng.standard_normal((nb, N, 4)) * 0.01
+    P = lambda a: np.ascontiguousarray(a).ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+    Nn.check(Nn.lib().sbm_set_learned_arrays(pb._h, P(w), P(U), P(V)), pb._h)
+    omega = mg.default_omega(prob.p)
+    for fp32 in (0, 1):
+        pb.set_vcycle_fp32(fp32)
+        wr, Ur, Vr = (_round(a, fp32) for a in (w, U, V))
+        b = _round(rng.standard_normal(L.n_dofs), fp32)
+        z = _round(rng.standard_normal(L.n_dofs), fp32)
+        Z, B = z.reshape(L.n_act, N), b.reshape(L.n_act, N)
+        for c in (0, 1):
+            zt = _dev(z, fp32)
+            pb.colour_update(-1, c, _dev(b, fp32), zt)
+            zn = _host(zt, L)
+            smp = _sample(L, rng)
+            mine = smp[(smp < L.n_col0) == (c == 0)]
+            r = B[mine] - L.cell_apply(mine, z)
+            corr = np.einsum('kij,kj->ki', np.linalg.inv(L.cell_diag_blocks(mine)), r)
+            j = pos[mine]
+            lb = j >= 0
+            corr[lb] = (wr[j[lb]])[:, None] * (corr[lb] + np.einsum('kia,kja,kj->ki', Ur[j[lb]], Vr[j[lb]], r[lb]))
+            err = _rel(zn[mine], Z[mine] + omega * corr)
+            print(f"[fullsize] balls128_q3 learned colour {c} fp32={fp32}: {len(mine)} cells "
+                  f"({int(lb.sum())} boundary), rel {err:.2e}", flush=True)
+            assert err <= (TOL32 if fp32 else TOL64)
+    Nn.check(Nn.lib().sbm_use_learned(pb._h, 0), pb._h)
