@@ -130,8 +130,8 @@ def time_apply_cold(pb, torch, fp32, reps=20, scrub_bytes=1 << 30):
 
 
 def copy_probe(torch, nbytes=1 << 30, reps=10):
-    """Achievable HBM bandwidth: a 1 GiB device-to-device copy (bytes read +
-    written per second), beside the vendor peak."""
+    """Achievable HBM bandwidth: a device-to-device copy of nbytes (1 GiB by
+    default; bytes read + written per second), beside the vendor peak."""
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -250,6 +250,9 @@ def main():
     tc64 = time_apply_cold(pb, torch, False)
     tc32 = time_apply_cold(pb, torch, True)
     copy_gbs = copy_probe(torch)
+    # the same probe moving as many bytes per launch as the finest colour update
+    # (launched back to back like it): what a plain copy of that size achieves
+    copy_small_gbs = copy_probe(torch, nbytes=int(smooth_pair_bytes(pb, True) / 4) // 8 * 8, reps=200)
     by64, by32 = apply_bytes(pb, False), apply_bytes(pb, True)
     bs32 = smooth_pair_bytes(pb, True) / 2          # per launch (average of the two colours)
     gbs64 = by64 / ta64 / 1e9
@@ -261,7 +264,8 @@ def main():
     roof = {"bound": "hbm", "kernel": "cellop_kernel<OP_SMOOTH> (finest-level colour update, FP32)",
             "achieved": gbs_s, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs_s / HBM_PEAK_GBS,
             "traffic": counter_traffic(prob.name, "smooth_fp32"), "bytes_per_launch": bs32,
-            "avg_launch_us": ts32 * 1e6}
+            "avg_launch_us": ts32 * 1e6, "copy_same_bytes_gbs": copy_small_gbs,
+            "frac_of_copy_same_bytes": gbs_s / copy_small_gbs}
     tr_a = counter_traffic(prob.name, "apply_fp64")
     roof_apply = {"bound": "hbm", "kernel": "cellop_kernel<OP_APPLY> (finest level, FP64)",
                   "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs64 / HBM_PEAK_GBS,
