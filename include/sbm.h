@@ -121,7 +121,9 @@ int sbm_default_options(int dim, int p, sbm_options *o);
  * D_K (Sec. 3.1, A_i = R_i A R_i^T) with their FP64 LU inverses, the
  * transfer maps (Sec. 3.2) and the dense coarsest-level inverse.  Uploads
  * everything to o->device.  Synchronous.  On success *out owns all of it.
- * Errors: SBM_EINVAL (arguments), SBM_ESINGULAR, SBM_EGEOM, SBM_ENOMEM, SBM_EDEVICE. */
+ * Errors: SBM_EINVAL (arguments, or a level with no active cell: an empty
+ * domain, or coarsening allowed down to a mesh with no cell centre inside
+ * the domain), SBM_ESINGULAR, SBM_EGEOM, SBM_ENOMEM, SBM_EDEVICE. */
 int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, struct sbm_problem **out);
 
 int sbm_layout_info(const struct sbm_problem *pb, sbm_layout *out);

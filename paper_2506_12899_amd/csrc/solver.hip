@@ -537,6 +537,18 @@ int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_pro
         }
         pb->levels.assign(f2c.rbegin(), f2c.rend());
     }
+    // every level must hold unknowns: the centre rule can leave a level empty
+    // (no cell centre inside the domain: an empty domain, or a small one on a
+    // coarse mesh when coarse_dofs / coarse_min allow coarsening that far)
+    for (const HostLevel &L : pb->levels) {
+        if (L.n_act == 0) {
+            pb->last_error = "level n = " + std::to_string(L.n) + ", p = " + std::to_string(L.p) +
+                             " has no active cell (no cell centre inside the domain): refine the mesh or raise "
+                             "coarse_dofs / coarse_min";
+            *out = pb;
+            return SBM_EINVAL;
+        }
+    }
     for (size_t l = 1; l < pb->levels.size(); ++l) build_transfer(pb->levels[l - 1], pb->levels[l]);
     const size_t nlev = pb->levels.size();
     // coarsest dense matrix and its inverse

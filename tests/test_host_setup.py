@@ -115,3 +115,18 @@ def test_every_declared_symbol_is_exported():
     for nm in names:
         getattr(L, nm)
     assert {s[0] for s in native.SIGNATURES} >= names
+
+
+def test_levels_without_active_cells_rejected():
+    """Degenerate hierarchies: a domain holding no cell centre, and a small one
+    on a mesh coarsened (coarse_dofs = 0) below the point where any coarse
+    cell centre lies inside it.  Setup refuses both with a message instead of
+    handing empty levels to the device path."""
+    from paper_2506_12899_amd.problem import Problem
+    small = workloads.balls([[0.0, 0.0]], [0.2])       # centres of the 4^2 mesh lie 0.354 away
+    for n, kw in ((4, {}), (32, {"coarse_dofs": 0})):
+        with pytest.raises(native.SbmError, match="no active cell"):
+            Problem(small, n, 1, device=-1, **kw)
+    # the same domain with the default coarsest size stops while levels hold cells
+    pb = _problem(small, 32, 1)
+    assert all(pb.level_info(l)["n_active"] > 0 for l in range(pb.n_levels))
