@@ -114,7 +114,7 @@ typedef struct {
 int sbm_default_options(int dim, int p, sbm_options *o);
 
 /* Build the hierarchy for geometry g, n^dim background cells and degree p
- * (1 <= p <= 3, dim in {2, 3}; n >= 1): per level the centre-inside active
+ * (1 <= p <= 3, dim in {2, 3}; n >= 1 and n^dim < 2^31): per level the centre-inside active
  * set (phi(cell centre) < 0), red-black order, neighbour table, surrogate
  * faces, closest points and shifts at the (p_l+1)^(dim-1) Gauss points of
  * every surrogate face (Sec. 4.2: once per level, stored), the cell blocks

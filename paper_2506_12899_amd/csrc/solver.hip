@@ -461,6 +461,8 @@ int sbm_destroy(sbm_problem *pb) {
 
 int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_problem **out) {
     if (!g || !out || n < 1 || p < 1 || p > 3 || (g->dim != 2 && g->dim != 3)) return SBM_EINVAL;
+    // cells are indexed by int: the background mesh holds at most 2^31 - 1 cells
+    if ((g->dim == 2 ? (double)n * n : (double)n * n * n) > 2147483647.0) return SBM_EINVAL;
     *out = nullptr;
     sbm_problem *pb = new (std::nothrow) sbm_problem();
     if (!pb) return SBM_ENOMEM;

@@ -75,6 +75,9 @@ def test_invalid_arguments_rejected():
         Problem(geo, 8, 4, device=-1)
     with pytest.raises(native.SbmError):
         Problem(geo, 0, 1, device=-1)
+    # a background mesh beyond int cell indices (n^2 >= 2^31) is refused before any allocation
+    with pytest.raises(native.SbmError):
+        Problem(geo, 46341, 1, device=-1)
     with pytest.raises(native.SbmError):
         Problem(geo, 8, 1, device=-1, ext=3)
     pb = _problem(geo, 8, 1)
