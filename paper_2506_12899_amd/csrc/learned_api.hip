@@ -2,6 +2,7 @@
 // BF16 inference and installation into the smoother).  See mlp.hip.
 #include <cmath>
 #include <cstring>
+#include <new>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -95,13 +96,24 @@ int sbm_boundary_cells(const sbm_problem *pb, int *n_boundary, int *cells, long 
     return SBM_OK;
 }
 
-int sbm_boundary_features(const sbm_problem *pb, double *out, long long cap) {
+static int boundary_features_body(const sbm_problem *pb, double *out, long long cap) {
     if (!pb || !out) return SBM_EINVAL;
     std::vector<double> F;
     features(pb, F);
     if (cap < (long long)F.size()) return SBM_EINVAL;
     std::memcpy(out, F.data(), F.size() * sizeof(double));
     return SBM_OK;
+}
+
+// (host containers throw std::bad_alloc; nothing may leave through the C ABI)
+int sbm_boundary_features(const sbm_problem *pb, double *out, long long cap) {
+    try {
+        return boundary_features_body(pb, out, cap);
+    } catch (const std::bad_alloc &) {
+        return SBM_ENOMEM;
+    } catch (...) {
+        return SBM_EINVAL;
+    }
 }
 
 int sbm_boundary_samples(sbm_problem *pb, const double *r, const double *e, double *R, double *BR, double *E) {
@@ -114,7 +126,7 @@ int sbm_boundary_samples(sbm_problem *pb, const double *r, const double *e, doub
     return SBM_OK;
 }
 
-int sbm_set_learned(sbm_problem *pb, const float *params, int width) {
+static int set_learned_body(sbm_problem *pb, const float *params, int width) {
     if (!pb || pb->host_only) return SBM_EINVAL;
     if (!params) {
         pb->learned_on = false;
@@ -158,7 +170,18 @@ int sbm_set_learned(sbm_problem *pb, const float *params, int width) {
     return SBM_OK;
 }
 
-int sbm_set_learned_arrays(sbm_problem *pb, const double *w, const double *U, const double *V) {
+// (host containers throw std::bad_alloc; nothing may leave through the C ABI)
+int sbm_set_learned(sbm_problem *pb, const float *params, int width) {
+    try {
+        return set_learned_body(pb, params, width);
+    } catch (const std::bad_alloc &) {
+        return SBM_ENOMEM;
+    } catch (...) {
+        return SBM_EINVAL;
+    }
+}
+
+static int set_learned_arrays_body(sbm_problem *pb, const double *w, const double *U, const double *V) {
     if (!pb || pb->host_only || !w || !U || !V) return SBM_EINVAL;
     auto &D64 = pb->dev64.back();
     auto &D32 = pb->dev32.back();
@@ -181,6 +204,17 @@ int sbm_set_learned_arrays(sbm_problem *pb, const double *w, const double *U, co
         return SBM_EDEVICE;
     pb->learned_on = true;
     return SBM_OK;
+}
+
+// (host containers throw std::bad_alloc; nothing may leave through the C ABI)
+int sbm_set_learned_arrays(sbm_problem *pb, const double *w, const double *U, const double *V) {
+    try {
+        return set_learned_arrays_body(pb, w, U, V);
+    } catch (const std::bad_alloc &) {
+        return SBM_ENOMEM;
+    } catch (...) {
+        return SBM_EINVAL;
+    }
 }
 
 int sbm_use_learned(sbm_problem *pb, int on) {

@@ -459,13 +459,14 @@ int sbm_destroy(sbm_problem *pb) {
     return SBM_OK;
 }
 
-int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_problem **out) {
+static int setup_body(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_problem **out, sbm_problem **live) {
     if (!g || !out || n < 1 || p < 1 || p > 3 || (g->dim != 2 && g->dim != 3)) return SBM_EINVAL;
     // cells are indexed by int: the background mesh holds at most 2^31 - 1 cells
     if ((g->dim == 2 ? (double)n * n : (double)n * n * n) > 2147483647.0) return SBM_EINVAL;
     *out = nullptr;
     sbm_problem *pb = new (std::nothrow) sbm_problem();
     if (!pb) return SBM_ENOMEM;
+    *live = pb;
     if (o)
         pb->opt = *o;
     else
@@ -608,6 +609,23 @@ int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_pro
     return SBM_OK;
 }
 
+// Host containers throw std::bad_alloc; nothing may leave through the C ABI:
+// a failed setup releases what it had built.
+int sbm_setup(const sbm_geometry *g, int n, int p, const sbm_options *o, sbm_problem **out) {
+    sbm_problem *live = nullptr;
+    int rc = SBM_ENOMEM;
+    try {
+        return setup_body(g, n, p, o, out, &live);
+    } catch (const std::bad_alloc &) {
+        rc = SBM_ENOMEM;
+    } catch (...) {
+        rc = SBM_EINVAL;
+    }
+    if (out) *out = nullptr;
+    if (live) sbm_destroy(live);
+    return rc;
+}
+
 int sbm_layout_info(const sbm_problem *pb, sbm_layout *o) {
     if (!pb || !o) return SBM_EINVAL;
     const HostLevel &L = pb->levels.back();
@@ -657,7 +675,7 @@ int sbm_shifts(const sbm_problem *pb, int level, double *out, long long cap) {
     return SBM_OK;
 }
 
-int sbm_rhs(sbm_problem *pb, sbm_field_fn f, sbm_field_fn g, void *user, double *b_dev) {
+static int rhs_body(sbm_problem *pb, sbm_field_fn f, sbm_field_fn g, void *user, double *b_dev) {
     if (!pb || pb->host_only || !f || !g || !b_dev) return SBM_EINVAL;
     const HostLevel &L = pb->levels.back();
     const int d = L.d, n1 = L.n1, nc = L.nc, nf = L.nf;
@@ -738,6 +756,17 @@ int sbm_rhs(sbm_problem *pb, sbm_field_fn f, sbm_field_fn g, void *user, double 
     HIPCHK(hipMemcpyAsync(b_dev, b.data(), b.size() * sizeof(double), hipMemcpyHostToDevice, pb->stream));
     HIPCHK(hipStreamSynchronize(pb->stream));
     return SBM_OK;
+}
+
+// (host containers throw std::bad_alloc; nothing may leave through the C ABI)
+int sbm_rhs(sbm_problem *pb, sbm_field_fn f, sbm_field_fn g, void *user, double *b_dev) {
+    try {
+        return rhs_body(pb, f, g, user, b_dev);
+    } catch (const std::bad_alloc &) {
+        return SBM_ENOMEM;
+    } catch (...) {
+        return SBM_EINVAL;
+    }
 }
 
 int sbm_apply(sbm_problem *pb, const void *x, void *y, int fp32) {
@@ -826,7 +855,7 @@ int sbm_sync(sbm_problem *pb) {
     return SBM_OK;
 }
 
-int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st) {
+static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st) {
     if (!pb || pb->host_only || !b || !x || b == x || m < 1 || m > 30 || max_iter < 1 || !(tol > 0)) return SBM_EINVAL;
     auto t0 = std::chrono::steady_clock::now();
     const HostLevel &L = pb->levels.back();
@@ -1003,6 +1032,17 @@ int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, in
     local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (st) *st = local;
     return status;
+}
+
+// (host containers throw std::bad_alloc; nothing may leave through the C ABI)
+int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st) {
+    try {
+        return solve_body(pb, b, x, tol, m, max_iter, st);
+    } catch (const std::bad_alloc &) {
+        return SBM_ENOMEM;
+    } catch (...) {
+        return SBM_EINVAL;
+    }
 }
 
 }  // extern "C"
