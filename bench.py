@@ -267,9 +267,11 @@ def main():
             "avg_launch_us": ts32 * 1e6, "copy_same_bytes_gbs": copy_small_gbs,
             "frac_of_copy_same_bytes": gbs_s / copy_small_gbs}
     tr_a = counter_traffic(prob.name, "apply_fp64")
+    copy_apply_gbs = copy_probe(torch, nbytes=int(by64 / 2) // 8 * 8, reps=200)
     roof_apply = {"bound": "hbm", "kernel": "cellop_kernel<OP_APPLY> (finest level, FP64)",
                   "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs64 / HBM_PEAK_GBS,
-                  "traffic": tr_a, "bytes_per_launch": by64, "avg_launch_us": ta64 * 1e6}
+                  "traffic": tr_a, "bytes_per_launch": by64, "avg_launch_us": ta64 * 1e6,
+                  "copy_same_bytes_gbs": copy_apply_gbs, "frac_of_copy_same_bytes": gbs64 / copy_apply_gbs}
     out = {
         "metric": METRIC, "value": t32, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": t32 * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
