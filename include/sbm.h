@@ -82,12 +82,29 @@ typedef struct {
                           /* coarse_dofs active DoFs (default 2048); the last level is solved */
                           /* with a dense inverse (at most 4096 DoFs)                         */
     int vcycle_fp32;      /* sbm_solve: 0 = FP64 V-cycle, 1 = FP32 V-cycle (default 0)        */
-    int allow_singular;   /* 1: shift near-singular blocks by 1e-10 |D_K| instead of failing  */
+    int allow_singular;   /* 1: do not fail on near-singular blocks; EVERY cell block is then */
+                          /* inverted as (D_K + 1e-10 max|D_K| I)^-1 (not only the singular  */
+                          /* ones), so the smoothing step keeps its repeated colour update  */
     int fuse_transfers;   /* V-cycle launches (same arithmetic either way).  1 (default): the
                              residual-restriction kernel also forms the coarser level's first
                              colour-0 update from zero, and the last colour updates of a
                              level add its final z into the finer level (the FP32 cycle's
                              finest level writes z in FP64 there).  0: separate kernels   */
+    int penalty_p;        /* degree in the penalties: 0 (default) = each level's own degree p_l,
+                             q >= 1 = sigma_F = c_F (q+1)^2 / h_l, sigma_Gamma = c_G (q+1)^2 / h_l
+                             on every level (one penalty constant across the hierarchy)    */
+    double lambda_frac;   /* active-cell rule (Sec. 2.1, Sec. 4.1): 0 (default) = the cell centre
+                             lies in Omega; lambda in (0, 1] = the volume fraction of the cell
+                             inside Omega exceeds lambda (lambda = 1: the whole cell inside),
+                             the fraction taken as the share of frac_m^dim cell-midpoint
+                             samples with phi < 0                                           */
+    int frac_m;           /* samples per direction for the volume fraction (default 16)     */
+    double stab;          /* smoother block stabilisation for near-singular cell blocks
+                             (Sec. 3.1 asks for one; 0 = none, default): singular values of
+                             a cell block below stab * s_int, s_int = smallest singular value
+                             of the level's interior block, are raised to that floor in its
+                             inverse, B_K = sum_i v_i u_i^T / max(sigma_i, stab s_int); the
+                             operator itself is unchanged                                   */
     int device;           /* HIP device ordinal (default 0); < 0 = host-only setup for tests:
                              no device data, the device entry points return SBM_EINVAL     */
     void *stream;         /* hipStream_t for all work (default NULL = null stream)            */

@@ -13,7 +13,12 @@ Readings of the paper used here (each is listed in the design notes):
     on linear functions;
   * sigma_F = c_F (p+1)^2 / h and sigma_Gamma = c_G (p+1)^2 / h, c_F = 2, c_G = 5;
   * a background cell is active iff phi(cell centre) < 0 (a cheap surrogate of
-    the volume-fraction rule of Sec. 2.1), on every level;
+    the volume-fraction rule of Sec. 2.1), on every level; or, with
+    lambda_frac > 0, iff its volume fraction inside Omega exceeds lambda, the
+    fraction taken by the midpoint rule on frac_m^d equal sub-cells (Sec. 4.1
+    uses cut-cell quadrature);
+  * penalty_p > 0: the penalties use that degree on every level (one constant
+    across the p-levels of a hierarchy) instead of the level's own degree;
   * the trial function carries the shift in the Nitsche terms, the test
     function does not (quasi-symmetric form, alpha = 1);
   * quadrature: (p+1)^d Gauss points per cell, (p+1)^(d-1) per face.
@@ -32,7 +37,8 @@ class Level:
     """One mesh level: active cells, faces, shifts and the DG-SBM matrix."""
 
     def __init__(self, geom, d, n, p, lo=-1.0, hi=1.0, c_F=2.0, c_G=5.0, alpha=1.0,
-                 ext=1, zero_shift=False, shifts=None, build_matrix=True):
+                 ext=1, zero_shift=False, shifts=None, build_matrix=True,
+                 penalty_p=0, lambda_frac=0.0, frac_m=16):
         if ext not in (0, 1):
             raise ValueError("ext must be 0 (first-order Taylor) or 1 (polynomial extrapolation)")
         self.geom, self.d, self.n, self.p = geom, d, n, p
@@ -40,8 +46,11 @@ class Level:
         self.lo, self.hi = float(lo), float(hi)
         self.h = (self.hi - self.lo) / n
         self.alpha = float(alpha)
-        self.sigma_F = c_F * (p + 1) ** 2 / self.h
-        self.sigma_G = c_G * (p + 1) ** 2 / self.h
+        # penalty degree: the level's own p, or one degree for the whole hierarchy
+        q = penalty_p if penalty_p > 0 else p
+        self.sigma_F = c_F * (q + 1) ** 2 / self.h
+        self.sigma_G = c_G * (q + 1) ** 2 / self.h
+        self.lambda_frac, self.frac_m = float(lambda_frac), int(frac_m)
         self.N = (p + 1) ** d
         self._classify()
         self._faces()
@@ -55,12 +64,39 @@ class Level:
             self.assemble()
 
     # ---------------------------------------------------------------- mesh
+    def volume_fractions(self, idx):
+        """Share of the frac_m^d midpoints of equal sub-cells of each cell that
+        lie in Omega (phi < 0): the midpoint-rule value of the volume fraction
+        that the active-cell rule of Sec. 2.1 thresholds."""
+        d, h, m = self.d, self.h, self.frac_m
+        sub = (basis.multi_indices(m, d) + 0.5) / m
+        out = np.zeros(len(idx))
+        todo = np.arange(len(idx))
+        if getattr(self.geom, "lipschitz", False) and len(idx):
+            # |phi| is at most the distance to Gamma: a cell whose centre is
+            # farther than half its diagonal from Gamma lies on one side
+            pc = self.geom.phi(self.lo + h * (idx + 0.5))
+            far = np.abs(pc) > 0.5 * np.sqrt(d) * h * (1 + 1e-12)
+            out[far] = (pc[far] < 0.0).astype(float)
+            todo = np.nonzero(~far)[0]
+        for a in range(0, len(todo), 256):
+            cc = todo[a:a + 256]
+            X = (self.lo + h * idx[cc])[:, None, :] + h * sub[None]
+            out[cc] = (self.geom.phi(X.reshape(-1, d)).reshape(-1, len(sub)) < 0.0).mean(axis=1)
+        return out
+
     def _classify(self):
         d, n, h = self.d, self.n, self.h
         idx = basis.multi_indices(n, d)          # every background cell, x fastest
         lin = np.arange(idx.shape[0])            # = i + n j + n^2 k
         centres = self.lo + h * (idx + 0.5)
-        active = self.geom.phi(centres) < 0.0 if idx.shape[0] else np.zeros(0, bool)
+        if self.lambda_frac > 0.0:
+            # Sec. 2.1: active iff the volume fraction inside Omega exceeds
+            # lambda (lambda = 1: the whole cell)
+            frac = self.volume_fractions(idx)
+            active = frac >= 1.0 if self.lambda_frac >= 1.0 else frac > self.lambda_frac
+        else:
+            active = self.geom.phi(centres) < 0.0 if idx.shape[0] else np.zeros(0, bool)
         colour = idx.sum(axis=1) % 2
         sel = np.nonzero(active)[0]
         order = sel[np.lexsort((lin[sel], colour[sel]))]
@@ -131,6 +167,15 @@ class Level:
         pts, w = basis.volume_points(p + 1, d)
         _, G = basis.tabulate(p, pts)
         return h ** d * np.einsum('q,qic,qjc->ij', w, G / h, G / h)
+
+    def interior_block(self):
+        """Diagonal block of a cell whose 2d neighbours are all active: the
+        volume term plus both sides' self terms of its 2d SIPG faces."""
+        D = self.volume_block()
+        for k in range(self.d):
+            B = self.interior_face_blocks(k)
+            D = D + B[0][0] + B[1][1]
+        return D
 
     def interior_face_blocks(self, k):
         """SIPG face terms on a face normal to e_k (Sec. 2.2, SIPG bilinear form).

@@ -27,7 +27,10 @@ _INSIDE_TOL = 1e-12
 
 
 class Balls:
-    """Union of balls |x - c_j| < r_j (one ball = disk / sphere)."""
+    """Union of balls |x - c_j| < r_j (one ball = disk / sphere).  phi is the
+    minimum of the balls' signed distances: 1-Lipschitz."""
+
+    lipschitz = True
 
     def __init__(self, centers, radii):
         self.centers = np.atleast_2d(np.asarray(centers, dtype=np.float64))

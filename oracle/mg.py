@@ -41,12 +41,31 @@ def default_omega(p):
     return 0.8 if p >= 3 else 1.0
 
 
+def cell_inverses(L, D, stab=0.0):
+    """Smoother inverses of the cell blocks D (k, N, N) of level L.
+
+    B_K = D_K^{-1} by LU with partial pivoting (LAPACK getrf/getri).
+    stab > 0: the stabilisation of near-singular cell blocks that Sec. 3.1
+    calls for (reading: a singular-value floor).  With D_K = U S V^T and the
+    floor f = stab * (smallest singular value of the level's interior block),
+    B_K = V diag(1 / max(s_i, f)) U^T; blocks whose singular values all reach
+    f keep the exact inverse."""
+    B = np.linalg.inv(D)
+    if stab > 0.0 and len(D):
+        floor = stab * np.linalg.svd(L.interior_block(), compute_uv=False)[-1]
+        U, s, Vt = np.linalg.svd(D)
+        low = s[:, -1] < floor
+        B[low] = np.einsum('kji,kj,klj->kil', Vt[low], 1.0 / np.maximum(s[low], floor), U[low])
+    return B
+
+
 class Hierarchy:
     """Levels coarsest first.  Geometric coarsening (p = 1) continues while n is
     even, n/2 >= coarse_min and the current level has more than coarse_dofs
     active DoFs; the last level is solved exactly."""
 
-    def __init__(self, geom, d, n, p, coarse_min=3, coarse_dofs=2048, omega=None, nu_pre=1, nu_post=1, **kw):
+    def __init__(self, geom, d, n, p, coarse_min=3, coarse_dofs=2048, omega=None, nu_pre=1, nu_post=1,
+                 stab=0.0, **kw):
         fine_first = [dg.Level(geom, d, n, q, **kw) for q in range(p, 0, -1)]
         nn = n
         while nn % 2 == 0 and nn // 2 >= coarse_min and fine_first[-1].n_dofs > coarse_dofs:
@@ -56,7 +75,8 @@ class Hierarchy:
         self.d = d
         self.omega = default_omega(p) if omega is None else float(omega)
         self.nu_pre, self.nu_post = nu_pre, nu_post
-        self.inv = [self._block_inverses(L) for L in self.levels]
+        self.stab = float(stab)
+        self.inv = [self._block_inverses(L, self.stab) for L in self.levels]
         self.P = [None] + [self._prolongation(self.levels[l - 1], self.levels[l])
                            for l in range(1, len(self.levels))]
         A0 = self.levels[0].A.toarray()
@@ -64,11 +84,10 @@ class Hierarchy:
         self.learned = None   # optional (omega_K, U_K, V_K) on the finest level
 
     @staticmethod
-    def _block_inverses(L):
-        """B_K = D_K^{-1} by LU with partial pivoting (LAPACK getrf/getri)."""
+    def _block_inverses(L, stab=0.0):
         if L.n_act == 0:
             return np.zeros((0, L.N, L.N))
-        return np.linalg.inv(L.D)
+        return cell_inverses(L, L.D, stab)
 
     @staticmethod
     def _prolongation(Lc, Lf):

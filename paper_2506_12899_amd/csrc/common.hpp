@@ -90,6 +90,7 @@ struct HostLevel {
     std::vector<int> bnd_cells;  // n_bnd
     std::vector<double> Dint, Bint;  // nc*nc row-major, B = D^{-1}
     std::vector<double> Dbnd, Bbnd;  // n_bnd * nc*nc
+    int n_clipped = 0;            // boundary blocks whose inverse the stabilisation changed
     // relation to the next coarser level (absent on level 0)
     int ratio = 1;                // 2 = h-transfer, 1 = p-transfer
     std::vector<int> parent;      // n_act -> coarse active index or -1

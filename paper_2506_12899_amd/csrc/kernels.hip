@@ -1302,6 +1302,9 @@ __global__ __launch_bounds__(64 * (1 << D)) void coarse_solve_prolong_kernel(int
 #pragma unroll
             for (int u = 0; u < 32; ++u) acc += j0 + 64 * u < n ? av[u] * xv[u] : 0.0;
         }
+        // lanes at or beyond the coarse DoF count never enter the row loop
+        // (a coarsest level of fewer than 64 DoFs) but may still own a child
+        if (lane >= n && F >= 0) zold = e.zf[(size_t)F * NCE + ao];
         if (t < 2 * N1E * 2) sP[t] = pv;
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         if (lane == 0) {

@@ -242,6 +242,115 @@ void coupling_block(const HostLevel &L, int k, int s, double *C) {
     }
 }
 
+// Volume-fraction rule (Sec. 2.1; Sec. 4.1 computes the fraction by cut-cell
+// quadrature): the fraction is the share of the m^d cell-midpoint samples
+// (cell split into m^d equal sub-cells) with phi < 0, and the cell is active
+// iff it exceeds lambda (lambda = 1: every sample inside).  A cell whose
+// centre and 2^d corners all lie on one side of Gamma is taken as wholly
+// inside or outside without sampling.
+static bool volume_fraction_active(const Geometry &g, const HostLevel &L, const int *mi, double lambda, int m) {
+    const int d = L.d;
+    double x[3];
+    for (int c = 0; c < d; ++c) x[c] = L.lo + L.h * (mi[c] + 0.5);
+    const bool in0 = g.phi(x) < 0.0;
+    bool mixed = false;
+    for (int v = 0; v < (1 << d) && !mixed; ++v) {
+        for (int c = 0; c < d; ++c) x[c] = L.lo + L.h * (mi[c] + ((v >> c) & 1));
+        mixed = (g.phi(x) < 0.0) != in0;
+    }
+    if (!mixed) return in0;
+    long long total = 1, inside = 0;
+    for (int c = 0; c < d; ++c) total *= m;
+    for (long long s = 0; s < total; ++s) {
+        long long t = s;
+        for (int c = 0; c < d; ++c) {
+            x[c] = L.lo + L.h * (mi[c] + ((t % m) + 0.5) / m);
+            t /= m;
+        }
+        inside += g.phi(x) < 0.0;
+    }
+    if (lambda >= 1.0) return inside == total;
+    return (double)inside > lambda * (double)total;
+}
+
+// Singular value decomposition of an n x n matrix by one-sided Jacobi
+// rotations (Hestenes): on return the columns of W are sigma_j u_j and V holds
+// the right singular vectors (D = W V^T), both column-major.
+static void jacobi_svd(const double *D, int n, std::vector<double> &W, std::vector<double> &V) {
+    W.assign((size_t)n * n, 0.0);
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) W[(size_t)j * n + i] = D[(size_t)i * n + j];
+    for (int j = 0; j < n; ++j) V[(size_t)j * n + j] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        bool rotated = false;
+        for (int a = 0; a < n - 1; ++a)
+            for (int b = a + 1; b < n; ++b) {
+                double *wa = &W[(size_t)a * n], *wb = &W[(size_t)b * n];
+                double al = 0, be = 0, ga = 0;
+                for (int i = 0; i < n; ++i) {
+                    al += wa[i] * wa[i];
+                    be += wb[i] * wb[i];
+                    ga += wa[i] * wb[i];
+                }
+                if (!(std::fabs(ga) > 1e-15 * std::sqrt(al * be))) continue;
+                rotated = true;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double tn = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / std::sqrt(1.0 + tn * tn), sn = cs * tn;
+                for (int i = 0; i < n; ++i) {
+                    const double p0 = wa[i], q0 = wb[i];
+                    wa[i] = cs * p0 - sn * q0;
+                    wb[i] = sn * p0 + cs * q0;
+                }
+                double *va = &V[(size_t)a * n], *vb = &V[(size_t)b * n];
+                for (int i = 0; i < n; ++i) {
+                    const double p0 = va[i], q0 = vb[i];
+                    va[i] = cs * p0 - sn * q0;
+                    vb[i] = sn * p0 + cs * q0;
+                }
+            }
+        if (!rotated) break;
+    }
+}
+
+static double smallest_singular_value(const double *D, int n) {
+    std::vector<double> W, V;
+    jacobi_svd(D, n, W, V);
+    double smin = INFINITY;
+    for (int j = 0; j < n; ++j) {
+        double s2 = 0;
+        for (int i = 0; i < n; ++i) s2 += W[(size_t)j * n + i] * W[(size_t)j * n + i];
+        smin = std::min(smin, std::sqrt(s2));
+    }
+    return smin;
+}
+
+// Stabilised inverse of a cell block: B = sum_j v_j u_j^T / max(sigma_j, floor)
+// (the exact inverse when every sigma_j >= floor).  Returns true if a singular
+// value was raised.  B: n x n row-major.
+static bool clipped_inverse(const double *D, int n, double floor_, double *B) {
+    std::vector<double> W, V;
+    jacobi_svd(D, n, W, V);
+    bool clipped = false;
+    for (int t = 0; t < n * n; ++t) B[t] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double *w = &W[(size_t)j * n];
+        double s2 = 0;
+        for (int i = 0; i < n; ++i) s2 += w[i] * w[i];
+        const double sg = std::sqrt(s2);
+        if (!(sg > 0.0)) continue;
+        if (sg < floor_) clipped = true;
+        const double f = 1.0 / (sg * std::max(sg, floor_));   // u_j = w / sigma
+        const double *v = &V[(size_t)j * n];
+        for (int r = 0; r < n; ++r) {
+            const double vr = v[r] * f;
+            for (int c = 0; c < n; ++c) B[(size_t)r * n + c] += vr * w[c];
+        }
+    }
+    return clipped;
+}
+
 int build_level(const Geometry &g, const sbm_options &o, int n, int p, HostLevel &L, std::string &err) {
     const int d = g.dim;
     L.d = d;
@@ -253,20 +362,26 @@ int build_level(const Geometry &g, const sbm_options &o, int n, int p, HostLevel
     L.lo = o.lo;
     L.h = (o.hi - o.lo) / n;
     L.ref = make_ref(p);
-    L.sigF = o.c_F * (p + 1) * (p + 1);
-    L.sigG = o.c_G * (p + 1) * (p + 1);
+    const int pp = o.penalty_p > 0 ? o.penalty_p : p;
+    L.sigF = o.c_F * (pp + 1) * (pp + 1);
+    L.sigG = o.c_G * (pp + 1) * (pp + 1);
     long long ncell = 1;
     for (int c = 0; c < d; ++c) ncell *= n;
     // classification (centre rule) and red-black lexicographic order
     std::vector<char> active(ncell);
     parallel_for(ncell, [&](long long lin) {
         long long t = lin;
+        int mi[3] = {0, 0, 0};
         double x[3];
         for (int c = 0; c < d; ++c) {
-            x[c] = L.lo + L.h * ((t % n) + 0.5);
+            mi[c] = (int)(t % n);
+            x[c] = L.lo + L.h * (mi[c] + 0.5);
             t /= n;
         }
-        active[lin] = g.phi(x) < 0.0;
+        if (o.lambda_frac > 0.0)
+            active[lin] = volume_fraction_active(g, L, mi, o.lambda_frac, o.frac_m);
+        else
+            active[lin] = g.phi(x) < 0.0;
     });
     L.cell_of.assign(ncell, -1);
     L.cells.clear();
@@ -385,6 +500,21 @@ int build_level(const Geometry &g, const sbm_options &o, int n, int p, HostLevel
     if (sing) {
         err = "singular boundary-cell block (set allow_singular to shift it)";
         return SBM_ESINGULAR;
+    }
+    L.n_clipped = 0;
+    if (o.stab > 0.0) {
+        // floor = stab * (smallest singular value of the interior block); a
+        // block needs the SVD only if 1 / |B_K|_F < floor (sigma_min >= 1/|B|_F)
+        const double floor_ = o.stab * smallest_singular_value(L.Dint.data(), nc);
+        std::atomic<int> nclip(0);
+        parallel_for(L.n_bnd, [&](long long b) {
+            double *B = &L.Bbnd[(size_t)b * nc * nc];
+            double f2 = 0;
+            for (int t = 0; t < nc * nc; ++t) f2 += B[t] * B[t];
+            if (1.0 / std::sqrt(f2) >= floor_) return;
+            if (clipped_inverse(&L.Dbnd[(size_t)b * nc * nc], nc, floor_, B)) nclip++;
+        });
+        L.n_clipped = nclip;
     }
     return SBM_OK;
 }

@@ -289,7 +289,7 @@ int resid_restrict(sbm_problem *pb, int l, const T *z, const T *b, T *bc, T *zc 
     // colour 1 (the cells map one to one, so the colour-0 part of bc is zero).
     const bool learned_here = pb->learned_on && l == (int)pb->levels.size() - 1 && Df.lw != nullptr;
     const bool c1_only = nch == 1 && pb->opt.nu_pre > 0 && pb->opt.omega == 1.0 && pb->opt.allow_singular == 0 &&
-                         !learned_here;
+                         pb->levels[l].n_clipped == 0 && !learned_here;
     KCHK(launch_resid_restrict<T>(Df.d, Df.p, Dc.n_act, nch, Dc.p + 1, nch == 1 ? nullptr : Df.rr_perm,
                                   nch == 1 ? nullptr : Df.rr_grp, z, b, bc, ca, Df.kref, tr, pb->stream,
                                   zc != nullptr ? &zs : nullptr, c1_only));
@@ -310,7 +310,9 @@ int prolong_add(sbm_problem *pb, int l, const T *zc, T *zf) {
 // inverses, the first colour-1 update zeroes the residual of every colour-1
 // cell, and nothing it depends on changes before the repeated colour-1 update
 // (cells of one colour do not couple), so that update adds zero up to rounding
-// and is skipped.  With omega != 1 or the learned correction it is kept.
+// and is skipped.  With omega != 1, inexact inverses (allow_singular: every
+// block is then (D_K + eps I)^-1; stabilised blocks of the level) or the
+// learned correction it is kept.
 // from_zero: z starts at zero; with b64 (FP32 cycle only) the right-hand side
 // is read in FP64 and its FP32 copy written to b on the way.  started: that
 // first colour-0 update from zero was already formed (by the finer level's
@@ -320,7 +322,8 @@ template <typename T>
 int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false, const double *b64 = nullptr,
               bool started = false, const EmitArgs<T> *em = nullptr) {
     const bool learned_here = pb->learned_on && l == (int)pb->levels.size() - 1;
-    const bool skip_repeat = pb->opt.omega == 1.0 && !learned_here;
+    const bool skip_repeat = pb->opt.omega == 1.0 && pb->opt.allow_singular == 0 && pb->levels[l].n_clipped == 0 &&
+                             !learned_here;
     int rc;
     if (started) {
         // nothing: z holds the zero-start colour-0 update
@@ -445,6 +448,10 @@ int sbm_default_options(int dim, int p, sbm_options *o) {
     o->vcycle_fp32 = 0;
     o->allow_singular = 0;
     o->fuse_transfers = 1;
+    o->penalty_p = 0;
+    o->lambda_frac = 0.0;
+    o->frac_m = 16;
+    o->stab = 0.0;
     o->device = 0;
     o->stream = nullptr;
     return SBM_OK;
@@ -473,7 +480,8 @@ static int setup_body(const sbm_geometry *g, int n, int p, const sbm_options *o,
         sbm_default_options(g->dim, p, &pb->opt);
     sbm_options &op = pb->opt;
     if (!(op.hi > op.lo) || op.nu_pre < 0 || op.nu_post < 0 || op.coarse_min < 1 || op.coarse_dofs < 0 ||
-        (op.ext != 0 && op.ext != 1)) {
+        (op.ext != 0 && op.ext != 1) || op.penalty_p < 0 || op.penalty_p > 3 || !(op.lambda_frac >= 0.0) ||
+        op.lambda_frac > 1.0 || op.frac_m < 1 || op.frac_m > 64 || !(op.stab >= 0.0)) {
         delete pb;
         return SBM_EINVAL;
     }

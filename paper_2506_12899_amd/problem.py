@@ -16,6 +16,9 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+_FLOATS = (torch.float32, torch.float64)
+
+
 class Problem:
     """DG-SBM hierarchy for one geometry (see include/sbm.h, sbm_setup)."""
 
@@ -135,6 +138,30 @@ class Problem:
         info = self.level_info(level)
         return info["n_active"] * (info["p"] + 1) ** self.dim
 
+    def _vectors(self, *pairs, dtype=None):
+        """Check (tensor, level) pairs before any pointer reaches the library:
+        the C side sees only addresses, so a wrong length, dtype or device
+        would become an out-of-bounds device access.  Returns the common
+        dtype's fp32 flag."""
+        dt = dtype
+        for t, level in pairs:
+            if not isinstance(t, torch.Tensor):
+                raise TypeError("expected a torch tensor")
+            if t.dtype not in _FLOATS:
+                raise ValueError(f"vectors must be float32 or float64, got {t.dtype}")
+            if dt is None:
+                dt = t.dtype
+            elif t.dtype != dt:
+                raise ValueError(f"mixed dtypes in one call ({t.dtype} and {dt})")
+            if self.device is None or t.device != self.device:
+                raise ValueError(f"vector on {t.device}, problem on {self.device}")
+            if not t.is_contiguous():
+                raise ValueError("vectors must be contiguous")
+            want = self.level_dofs(level)
+            if t.numel() != want:
+                raise ValueError(f"vector of {t.numel()} entries where level {level} has {want} DoFs")
+        return int(dt == torch.float32)
+
     # ------------------------------------------------------------- data
     def rhs(self, f, g):
         """b (FP64 cuda tensor) for vectorised callables f(X), g(X) on (npts, dim) arrays."""
@@ -147,37 +174,49 @@ class Problem:
             return N.FIELD_FN(cb)
         cf, cg = wrap(f), wrap(g)
         b = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        self._vectors((b, -1), dtype=torch.float64)
         N.check(N.lib().sbm_rhs(self._h, cf, cg, None, _ptr(b)), self._h)
         return b
 
     # ------------------------------------------------------------- operators
     def apply(self, x, y=None):
         y = torch.empty_like(x) if y is None else y
-        N.check(N.lib().sbm_apply(self._h, _ptr(x), _ptr(y), int(x.dtype == torch.float32)), self._h)
+        f32 = self._vectors((x, -1), (y, -1))
+        N.check(N.lib().sbm_apply(self._h, _ptr(x), _ptr(y), f32), self._h)
         return y
 
     def vcycle(self, r, z=None):
         z = torch.empty_like(r) if z is None else z
-        N.check(N.lib().sbm_vcycle(self._h, _ptr(r), _ptr(z), int(r.dtype == torch.float32)), self._h)
+        f32 = self._vectors((r, -1), (z, -1))
+        N.check(N.lib().sbm_vcycle(self._h, _ptr(r), _ptr(z), f32), self._h)
         return z
 
     def level_apply(self, level, x, y=None):
         y = torch.empty_like(x) if y is None else y
-        N.check(N.lib().sbm_level_apply(self._h, level, _ptr(x), _ptr(y), int(x.dtype == torch.float32)), self._h)
+        f32 = self._vectors((x, level), (y, level))
+        N.check(N.lib().sbm_level_apply(self._h, level, _ptr(x), _ptr(y), f32), self._h)
         return y
 
     def colour_update(self, level, colour, b, z):
-        N.check(N.lib().sbm_colour_update(self._h, level, colour, _ptr(b), _ptr(z),
-                                          int(z.dtype == torch.float32)), self._h)
+        f32 = self._vectors((b, level), (z, level))
+        N.check(N.lib().sbm_colour_update(self._h, level, colour, _ptr(b), _ptr(z), f32), self._h)
         return z
 
     def restrict(self, level, r, bc):
-        N.check(N.lib().sbm_restrict(self._h, level, _ptr(r), _ptr(bc), int(r.dtype == torch.float32)), self._h)
+        f32 = self._vectors((r, level), (bc, self._coarser(level)))
+        N.check(N.lib().sbm_restrict(self._h, level, _ptr(r), _ptr(bc), f32), self._h)
         return bc
 
     def prolong_add(self, level, zc, zf):
-        N.check(N.lib().sbm_prolong_add(self._h, level, _ptr(zc), _ptr(zf), int(zf.dtype == torch.float32)), self._h)
+        f32 = self._vectors((zc, self._coarser(level)), (zf, level))
+        N.check(N.lib().sbm_prolong_add(self._h, level, _ptr(zc), _ptr(zf), f32), self._h)
         return zf
+
+    def _coarser(self, level):
+        lv = self.n_levels - 1 if level == -1 else level
+        if not 1 <= lv < self.n_levels:
+            raise ValueError(f"level {level} has no coarser level")
+        return lv - 1
 
     def sync(self):
         N.check(N.lib().sbm_sync(self._h), self._h)
@@ -189,6 +228,7 @@ class Problem:
         if vcycle_fp32 is not None:
             self.set_vcycle_fp32(vcycle_fp32)
         x = torch.empty_like(b) if x is None else x
+        self._vectors((b, -1), (x, -1), dtype=torch.float64)
         st = N.Stats()
         status = N.check(N.lib().sbm_solve(self._h, _ptr(b), _ptr(x), tol, restart, max_iter, C.byref(st)), self._h)
         return x, dict(status=status, iterations=st.iterations, converged=bool(st.converged),

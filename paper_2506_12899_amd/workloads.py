@@ -136,6 +136,14 @@ def linear(a, c=0.0):
     return Solution("linear", u, f)
 
 
+# Solver options of the 3D Q3 workloads: the volume-fraction active-cell rule
+# (lambda = 0.65), one penalty degree (3) for the whole hierarchy and the
+# singular-value floor of the smoother's block inverses (1 x the interior
+# block's smallest singular value).  With the centre rule and per-level
+# penalties the cell-wise smoother diverges on these meshes.
+STABILISED_Q3 = {"lambda_frac": 0.65, "penalty_p": 3, "stab": 1.0}
+
+
 @dataclasses.dataclass
 class Problem:
     name: str
@@ -143,6 +151,7 @@ class Problem:
     n: int
     p: int
     solution: Solution
+    opts: dict = dataclasses.field(default_factory=dict)   # sbm_options fields beyond the defaults
 
     @property
     def dim(self):
@@ -157,9 +166,9 @@ def problem(name):
     if name == "sphere64_q2":
         return Problem(name, balls([[0.0, 0.0, 0.0]], [0.75]), 64, 2, _sinprod(3))
     if name == "sphere96_q3":
-        return Problem(name, balls([[0.0, 0.0, 0.0]], [0.8]), 96, 3, _sinprod(3))
+        return Problem(name, balls([[0.0, 0.0, 0.0]], [0.8]), 96, 3, _sinprod(3), dict(STABILISED_Q3))
     if name == "balls128_q3":
-        return Problem(name, eight_balls(0), 128, 3, _sincosexp())
+        return Problem(name, eight_balls(0), 128, 3, _sincosexp(), dict(STABILISED_Q3))
     raise KeyError(name)
 
 

@@ -133,3 +133,35 @@ def test_levels_without_active_cells_rejected():
     # the same domain with the default coarsest size stops while levels hold cells
     pb = _problem(small, 32, 1)
     assert all(pb.level_info(l)["n_active"] > 0 for l in range(pb.n_levels))
+
+
+# the stabilised 3D Q3 form: volume-fraction rule, one penalty degree for the
+# hierarchy, singular-value floor of the smoother's block inverses
+STAB_CASES = [
+    ("sphere", workloads.balls([[0.03, -0.02, 0.01]], [0.8]), 12, 3, dict(lambda_frac=0.65, penalty_p=3, stab=1.0)),
+    ("union3", workloads.eight_balls(0), 16, 2, dict(lambda_frac=0.6, penalty_p=2, stab=1.0)),
+    ("star", workloads.star(0.6, 0.15, 5), 32, 3, dict(lambda_frac=0.5, stab=1.0)),
+    ("disk", workloads.balls([[0.03, -0.02]], [0.7]), 16, 2, dict(lambda_frac=1.0, penalty_p=2)),
+]
+
+
+@pytest.mark.parametrize("name,geo,n,p,kw", STAB_CASES)
+def test_stabilised_form_matches_oracle(name, geo, n, p, kw):
+    """Active sets by the volume-fraction rule, blocks with the hierarchy's
+    penalty degree and the floored inverses agree with the oracle's."""
+    pb = _problem(geo, n, p, **kw)
+    H = mg.Hierarchy(oracle_geometry(geo), geo.dim, n, p, **kw)
+    assert pb.n_levels == len(H.levels)
+    floored = 0
+    for l, L in enumerate(H.levels):
+        assert np.array_equal(pb.active_cells(l), L.cells), l
+        assert np.abs(pb.shifts(l) - L.shifts).max(initial=0.0) <= 1e-12
+        exact = np.linalg.inv(L.D[L.boundary_cells])
+        floored += int(np.sum(np.abs(exact - H.inv[l][L.boundary_cells]).max(axis=(1, 2)) > 0))
+        for K in L.boundary_cells:
+            D = pb.cell_block(int(K), l)
+            assert np.abs(D - L.D[K]).max() <= 1e-12 * np.abs(L.D[K]).max(), (l, K)
+            B = pb.cell_block(int(K), l, inverse=True)
+            assert np.abs(B - H.inv[l][K]).max() <= 1e-10 * np.abs(H.inv[l][K]).max(), (l, K)
+    if kw.get("stab", 0) > 0 and name != "star":
+        assert floored > 0      # the floor is exercised

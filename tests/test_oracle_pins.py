@@ -155,11 +155,16 @@ def _kron_dir(mats):
 
 
 @pytest.mark.parametrize("d,p", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)])
-def test_interior_blocks_closed_form(d, p):
+@pytest.mark.parametrize("penalty_p", [0, 3])
+def test_interior_blocks_closed_form(d, p, penalty_p):
+    """penalty_p = 0: sigma_F = 2 (p+1)^2 / h of the level's own degree;
+    penalty_p = q: 2 (q+1)^2 / h whatever the level's degree."""
     geo = DISK if d == 2 else SPHERE
     n = 10 if d == 2 else 8
-    L = dg.Level(geo, d, n, p)
-    h, sig = L.h, L.sigma_F
+    L = dg.Level(geo, d, n, p, penalty_p=penalty_p)
+    q = penalty_p if penalty_p else p
+    h = L.h
+    sig = 2.0 * (q + 1) ** 2 / h
     M, K, e0, e1, g0, g1 = _poly_1d(p)
     T = K / h - 0.5 * (np.outer(e1, g1) + np.outer(g1, e1)) / h \
         + 0.5 * (np.outer(e0, g0) + np.outer(g0, e0)) / h + sig * (np.outer(e1, e1) + np.outer(e0, e0))
@@ -177,6 +182,80 @@ def test_interior_blocks_closed_form(d, p):
         assert np.abs(blk - Ck).max() <= 1e-13 * np.abs(Ck).max()
         blkT = Ad[Kp * L.N:(Kp + 1) * L.N, K0 * L.N:(K0 + 1) * L.N].toarray()
         assert np.abs(blkT - Ck.T).max() <= 1e-13 * np.abs(Ck).max()
+
+
+# ------------------------------------------- volume-fraction active-cell rule
+class _Plane:
+    """Half-space x_0 < c (only phi is needed for the classification)."""
+
+    def __init__(self, c):
+        self.c = c
+
+    def phi(self, X):
+        return np.atleast_2d(X)[:, 0] - self.c
+
+
+@pytest.mark.parametrize("c", [0.1, -0.37, 0.6251])
+@pytest.mark.parametrize("m", [4, 16])
+def test_volume_fraction_of_plane_cut_closed_form(c, m):
+    """A cell [x0, x0 + h] cut by the plane x = c: of the m midpoints
+    x0 + h (a + 1/2) / m exactly ceil(t m - 1/2) (clipped to [0, m]) lie below
+    c, t = (c - x0) / h; the fraction does not depend on the other directions."""
+    L = dg.Level(_Plane(c), 2, 8, 1, zero_shift=True, build_matrix=False, frac_m=m)
+    idx = basis.multi_indices(8, 2)
+    frac = L.volume_fractions(idx)
+    t = (c - (L.lo + L.h * idx[:, 0])) / L.h
+    expect = np.clip(np.ceil(t * m - 0.5), 0, m) / m
+    assert np.array_equal(frac, expect)
+
+
+@pytest.mark.parametrize("lam", [0.25, 0.5, 0.75, 1.0])
+def test_lambda_rule_selects_cells_by_fraction(lam):
+    """Sec. 2.1: a cell is active iff its fraction exceeds lambda (lambda = 1:
+    the whole cell); on a plane cut the active columns are those whose
+    fraction passes, and the total active volume matches the half-space."""
+    c = 0.23
+    L = dg.Level(_Plane(c), 2, 8, 1, zero_shift=True, build_matrix=False, lambda_frac=lam)
+    x0 = L.lo + L.h * np.arange(8)
+    t = np.clip((c - x0) / L.h, 0, 1)
+    frac = np.clip(np.ceil(t * 16 - 0.5), 0, 16) / 16
+    cols = np.nonzero(frac >= 1.0 if lam >= 1.0 else frac > lam)[0]
+    assert sorted(set(L.cells[:, 0].tolist())) == cols.tolist()
+    assert L.n_act == 8 * len(cols)
+
+
+def test_volume_fractions_sum_to_ball_volume():
+    """The fractions of all cells add up to the volume of the ball (midpoint
+    rule on a 2^-5-fine sub-grid of a 12^3 mesh: within 0.5 %)."""
+    L = dg.Level(SPHERE, 3, 12, 1, zero_shift=True, build_matrix=False, frac_m=16)
+    vol = L.volume_fractions(basis.multi_indices(12, 3)).sum() * L.h ** 3
+    assert abs(vol - 4.0 / 3.0 * math.pi * 0.75 ** 3) <= 5e-3 * vol
+
+
+# ------------------------------------------------ stabilised block inverses
+def test_floored_inverse_is_projector_like():
+    """B_K with singular values floored at f: B_K D_K = V diag(min(1, s/f)) V^T
+    is symmetric with eigenvalues min(1, s_i/f); blocks with s_min >= f keep
+    D_K^-1 exactly.  A transposed factor (U and V swapped) breaks symmetry."""
+    H = mg.Hierarchy(UNION3, 3, 12, 3, stab=1.0, lambda_frac=0.6, penalty_p=3)
+    L = H.fine
+    floor = 1.0 * np.linalg.svd(L.interior_block(), compute_uv=False)[-1]
+    nfloor = 0
+    for K in L.boundary_cells:
+        s = np.linalg.svd(L.D[K], compute_uv=False)
+        BD = H.inv[-1][K] @ L.D[K]
+        if s[-1] >= floor:
+            assert np.abs(BD - np.eye(L.N)).max() <= 1e-9
+            continue
+        nfloor += 1
+        assert np.abs(BD - BD.T).max() <= 1e-9 * np.abs(BD).max()
+        ev = np.sort(np.linalg.eigvalsh(0.5 * (BD + BD.T)))
+        assert np.allclose(ev, np.sort(np.minimum(1.0, s / floor)), atol=1e-8)
+        U, ss, Vt = np.linalg.svd(L.D[K])
+        wrong = (U * (1.0 / np.maximum(ss, floor))) @ Vt        # planted: factors swapped
+        WD = wrong @ L.D[K]
+        assert np.abs(WD - WD.T).max() > 1e-3 * np.abs(WD).max()
+    assert nfloor > 0
 
 
 # ----------------------------------------------------- P4 dense direct solve
@@ -198,7 +277,6 @@ def test_mg_gmres_matches_dense_solve(d, n, p):
     assert np.linalg.norm(x - xd) <= kappa * 1e-10 * np.linalg.norm(xd)
 
 
-# ------------------------------------------------------------------ P5 rates
 # ------------------------------------------------ V-cycle composition pins
 class _Sweep0101(mg.Hierarchy):
     """Planted mistake: smoothing step visits the colours 0, 1, 0, 1."""
@@ -285,6 +363,7 @@ def test_vcycle_contracts_on_unshifted_problem(geo, d, n, p):
         assert (rho <= 0.8) == ok, (cls.__name__, rho)
 
 
+# ------------------------------------------------------------------ P5 rates
 def _rate(geo, d, ns, p, ext, sol):
     errs = []
     for n in ns:
