@@ -99,6 +99,12 @@ typedef struct {
                              the fraction taken as the share of frac_m^dim cell-midpoint
                              samples with phi < 0                                           */
     int frac_m;           /* samples per direction for the volume fraction (default 16)     */
+    int min_neighbours;   /* 0 (default) or k >= 1: after the active-cell rule, cells with fewer
+                             than k active face neighbours are dropped, repeatedly, until every
+                             active cell has at least k (the k-core of the face-adjacency graph
+                             of the active cells) on the finest mesh (its p-levels); removes
+                             cells that hang on by one or two faces, whose blocks and patches
+                             are near-singular at p = 3; coarser meshes keep the plain rule */
     double stab;          /* smoother block stabilisation for near-singular cell blocks
                              (Sec. 3.1 asks for one; 0 = none, default): singular values of
                              a cell block below stab * s_int, s_int = smallest singular value

@@ -19,6 +19,8 @@ Readings of the paper used here (each is listed in the design notes):
     uses cut-cell quadrature);
   * penalty_p > 0: the penalties use that degree on every level (one constant
     across the p-levels of a hierarchy) instead of the level's own degree;
+  * min_neighbours = k > 0: the active set is then reduced to its k-core (cells
+    with fewer than k active face neighbours dropped until none is left);
   * the trial function carries the shift in the Nitsche terms, the test
     function does not (quasi-symmetric form, alpha = 1);
   * quadrature: (p+1)^d Gauss points per cell, (p+1)^(d-1) per face.
@@ -38,7 +40,7 @@ class Level:
 
     def __init__(self, geom, d, n, p, lo=-1.0, hi=1.0, c_F=2.0, c_G=5.0, alpha=1.0,
                  ext=1, zero_shift=False, shifts=None, build_matrix=True,
-                 penalty_p=0, lambda_frac=0.0, frac_m=16):
+                 penalty_p=0, lambda_frac=0.0, frac_m=16, min_neighbours=0):
         if ext not in (0, 1):
             raise ValueError("ext must be 0 (first-order Taylor) or 1 (polynomial extrapolation)")
         self.geom, self.d, self.n, self.p = geom, d, n, p
@@ -51,6 +53,7 @@ class Level:
         self.sigma_F = c_F * (q + 1) ** 2 / self.h
         self.sigma_G = c_G * (q + 1) ** 2 / self.h
         self.lambda_frac, self.frac_m = float(lambda_frac), int(frac_m)
+        self.min_neighbours = int(min_neighbours)
         self.N = (p + 1) ** d
         self._classify()
         self._faces()
@@ -97,6 +100,8 @@ class Level:
             active = frac >= 1.0 if self.lambda_frac >= 1.0 else frac > self.lambda_frac
         else:
             active = self.geom.phi(centres) < 0.0 if idx.shape[0] else np.zeros(0, bool)
+        if self.min_neighbours > 0:
+            active = self._k_core(active, self.min_neighbours)
         colour = idx.sum(axis=1) % 2
         sel = np.nonzero(active)[0]
         order = sel[np.lexsort((lin[sel], colour[sel]))]
@@ -107,6 +112,27 @@ class Level:
         self.cell_of = -np.ones(n ** d, dtype=np.int64)
         self.cell_of[order] = np.arange(self.n_act)
         self.n_dofs = self.n_act * self.N
+
+    def _k_core(self, active, k):
+        """Largest subset of the active cells in which every cell has at least
+        k active face neighbours (cells below k dropped until none is left)."""
+        d, n = self.d, self.n
+        act = active.reshape((n,) * d).copy()              # axis 0 = last coordinate
+        while True:
+            cnt = np.zeros(act.shape, dtype=int)
+            for ax in range(d):
+                pad = [(0, 0)] * d
+                pad[ax] = (1, 1)
+                p = np.pad(act, pad)
+                lo = [slice(None)] * d
+                hi = [slice(None)] * d
+                lo[ax] = slice(0, n)
+                hi[ax] = slice(2, n + 2)
+                cnt += p[tuple(lo)].astype(int) + p[tuple(hi)].astype(int)
+            drop = act & (cnt < k)
+            if not drop.any():
+                return act.reshape(-1)
+            act &= ~drop
 
     def lin_index(self, mi):
         mi = np.atleast_2d(mi)

@@ -20,7 +20,9 @@ Readings (listed in the design notes):
   * V(1,1), a pre-smoothing step starting from zero;
   * inactive DoFs are identically zero: restriction into an inactive coarse
     cell is dropped, prolongation from an inactive parent gives zero;
-  * coarse solver: a direct solve with the dense matrix of the coarsest level.
+  * coarse solver: a direct solve with the dense matrix of the coarsest level;
+  * min_neighbours (the k-core rule of the active set) shapes the finest mesh
+    only; the h-coarsened levels keep the plain active-cell rule.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -67,10 +69,11 @@ class Hierarchy:
     def __init__(self, geom, d, n, p, coarse_min=3, coarse_dofs=2048, omega=None, nu_pre=1, nu_post=1,
                  stab=0.0, **kw):
         fine_first = [dg.Level(geom, d, n, q, **kw) for q in range(p, 0, -1)]
+        ckw = {k: v for k, v in kw.items() if k != "min_neighbours"}   # finest mesh only
         nn = n
         while nn % 2 == 0 and nn // 2 >= coarse_min and fine_first[-1].n_dofs > coarse_dofs:
             nn //= 2
-            fine_first.append(dg.Level(geom, d, nn, 1, **kw))
+            fine_first.append(dg.Level(geom, d, nn, 1, **ckw))
         self.levels = fine_first[::-1]
         self.d = d
         self.omega = default_omega(p) if omega is None else float(omega)

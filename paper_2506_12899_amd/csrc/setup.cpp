@@ -273,6 +273,43 @@ static bool volume_fraction_active(const Geometry &g, const HostLevel &L, const 
     return (double)inside > lambda * (double)total;
 }
 
+// Keep the k-core of the active cells' face-adjacency graph: drop every cell
+// with fewer than k active face neighbours, and again for the neighbours that
+// fall below k, until none is left to drop (the result does not depend on the
+// order of removal).
+static void prune_active(std::vector<char> &active, int n, int d, int k) {
+    const long long ncell = (long long)active.size();
+    long long stride[3] = {1, n, (long long)n * n};
+    auto count = [&](long long lin) {
+        int c = 0;
+        long long t = lin;
+        for (int a = 0; a < d; ++a) {
+            const int m = (int)(t % n);
+            t /= n;
+            if (m > 0 && active[lin - stride[a]]) ++c;
+            if (m < n - 1 && active[lin + stride[a]]) ++c;
+        }
+        return c;
+    };
+    std::vector<long long> queue;
+    for (long long lin = 0; lin < ncell; ++lin)
+        if (active[lin] && count(lin) < k) queue.push_back(lin);
+    while (!queue.empty()) {
+        const long long lin = queue.back();
+        queue.pop_back();
+        if (!active[lin]) continue;
+        active[lin] = 0;
+        long long t = lin;
+        for (int a = 0; a < d; ++a) {
+            const int m = (int)(t % n);
+            t /= n;
+            const long long nb[2] = {m > 0 ? lin - stride[a] : -1, m < n - 1 ? lin + stride[a] : -1};
+            for (long long q : nb)
+                if (q >= 0 && active[q] && count(q) < k) queue.push_back(q);
+        }
+    }
+}
+
 // Singular value decomposition of an n x n matrix by one-sided Jacobi
 // rotations (Hestenes): on return the columns of W are sigma_j u_j and V holds
 // the right singular vectors (D = W V^T), both column-major.
@@ -351,7 +388,8 @@ static bool clipped_inverse(const double *D, int n, double floor_, double *B) {
     return clipped;
 }
 
-int build_level(const Geometry &g, const sbm_options &o, int n, int p, HostLevel &L, std::string &err) {
+int build_level(const Geometry &g, const sbm_options &o, int n, int p, bool finest_mesh, HostLevel &L,
+                std::string &err) {
     const int d = g.dim;
     L.d = d;
     L.n = n;
@@ -383,6 +421,9 @@ int build_level(const Geometry &g, const sbm_options &o, int n, int p, HostLevel
         else
             active[lin] = g.phi(x) < 0.0;
     });
+    // the k-core rule shapes the finest mesh (all its p-levels); the
+    // h-coarsened p = 1 levels keep the plain rule
+    if (o.min_neighbours > 0 && finest_mesh) prune_active(active, n, d, o.min_neighbours);
     L.cell_of.assign(ncell, -1);
     L.cells.clear();
     for (int col = 0; col < 2; ++col)

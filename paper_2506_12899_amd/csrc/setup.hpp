@@ -9,7 +9,8 @@
 
 namespace sbm {
 
-int build_level(const Geometry &g, const sbm_options &o, int n, int p, HostLevel &L, std::string &err);
+int build_level(const Geometry &g, const sbm_options &o, int n, int p, bool finest_mesh, HostLevel &L,
+                std::string &err);
 void build_transfer(const HostLevel &Lc, HostLevel &Lf);
 void embedding_1d(const HostLevel &Lc, const HostLevel &Lf, double P1[2][MAXN1][MAXN1]);
 int coarse_matrix(const HostLevel &L, double alpha, int ext, std::vector<double> &A);

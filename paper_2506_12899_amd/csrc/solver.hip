@@ -451,6 +451,7 @@ int sbm_default_options(int dim, int p, sbm_options *o) {
     o->penalty_p = 0;
     o->lambda_frac = 0.0;
     o->frac_m = 16;
+    o->min_neighbours = 0;
     o->stab = 0.0;
     o->device = 0;
     o->stream = nullptr;
@@ -481,7 +482,8 @@ static int setup_body(const sbm_geometry *g, int n, int p, const sbm_options *o,
     sbm_options &op = pb->opt;
     if (!(op.hi > op.lo) || op.nu_pre < 0 || op.nu_post < 0 || op.coarse_min < 1 || op.coarse_dofs < 0 ||
         (op.ext != 0 && op.ext != 1) || op.penalty_p < 0 || op.penalty_p > 3 || !(op.lambda_frac >= 0.0) ||
-        op.lambda_frac > 1.0 || op.frac_m < 1 || op.frac_m > 64 || !(op.stab >= 0.0)) {
+        op.lambda_frac > 1.0 || op.frac_m < 1 || op.frac_m > 64 || !(op.stab >= 0.0) || op.min_neighbours < 0 ||
+        op.min_neighbours > 2 * g->dim) {
         delete pb;
         return SBM_EINVAL;
     }
@@ -532,7 +534,7 @@ static int setup_body(const sbm_geometry *g, int n, int p, const sbm_options *o,
         for (int q = p;; ) {
             f2c.emplace_back();
             std::string err;
-            int rc = build_level(G, op, nn, q, f2c.back(), err);
+            int rc = build_level(G, op, nn, q, nn == n, f2c.back(), err);
             if (rc) {
                 pb->last_error = err;
                 *out = pb;  // caller can read the message, must destroy

@@ -143,7 +143,7 @@ _LEVELS = {}
 
 def _level_opts(prob):
     """The workload's options that shape a level (not the smoother's)."""
-    return {k: v for k, v in prob.opts.items() if k in ("lambda_frac", "penalty_p", "frac_m")}
+    return {k: v for k, v in prob.opts.items() if k in ("lambda_frac", "penalty_p", "frac_m", "min_neighbours")}
 
 
 def _coarser(prob, n, p):

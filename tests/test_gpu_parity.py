@@ -79,7 +79,7 @@ def _check32_cycle(z32, H32, r, ref64, what=""):
     assert np.abs(z32 - ref64).max(initial=0) <= 10 * bar * np.abs(ref64).max(initial=0), what
 
 
-STAB3 = {"lambda_frac": 0.65, "penalty_p": 3, "stab": 1.0}
+STAB3 = dict(workloads.STABILISED_Q3)
 CASES = [
     ("disk_q1", workloads.balls([[0.03, -0.02]], [0.7]), 32, 1, {}),
     ("disk_q2", workloads.balls([[0.03, -0.02]], [0.7]), 24, 2, {}),
@@ -278,6 +278,7 @@ SOLVE3_CASES = [
     ("sphere_q3_stab", workloads.balls([[0.0, 0.0, 0.0]], [0.8]), 16, 3, STAB3),
     ("sphere_q3_stab_fp32", workloads.balls([[0.0, 0.0, 0.0]], [0.8]), 16, 3, dict(STAB3, vcycle_fp32=1)),
     ("two_balls_q3_stab", workloads.balls([[-0.3, 0.05, 0.0], [0.35, -0.05, 0.02]], [0.55, 0.45]), 16, 3, STAB3),
+    ("union3_q3_stab", workloads.eight_balls(0), 16, 3, STAB3),
 ]
 
 

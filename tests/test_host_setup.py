@@ -138,7 +138,8 @@ def test_levels_without_active_cells_rejected():
 # the stabilised 3D Q3 form: volume-fraction rule, one penalty degree for the
 # hierarchy, singular-value floor of the smoother's block inverses
 STAB_CASES = [
-    ("sphere", workloads.balls([[0.03, -0.02, 0.01]], [0.8]), 12, 3, dict(lambda_frac=0.65, penalty_p=3, stab=1.0)),
+    ("sphere", workloads.balls([[0.03, -0.02, 0.01]], [0.8]), 12, 3, dict(workloads.STABILISED_Q3)),
+    ("union3_core", workloads.eight_balls(0), 16, 3, dict(workloads.STABILISED_Q3)),
     ("union3", workloads.eight_balls(0), 16, 2, dict(lambda_frac=0.6, penalty_p=2, stab=1.0)),
     ("star", workloads.star(0.6, 0.15, 5), 32, 3, dict(lambda_frac=0.5, stab=1.0)),
     ("disk", workloads.balls([[0.03, -0.02]], [0.7]), 16, 2, dict(lambda_frac=1.0, penalty_p=2)),
