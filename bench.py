@@ -1,13 +1,15 @@
 """Benchmark: time to a 1e-8 true relative residual, and DG-apply throughput.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload star512_q2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere96_q3]
 
 One step is one full solve of the hot path -- FGMRES(30) preconditioned by
 the hp-multigrid V-cycle with the red-black cell-block smoother, h/p transfers
 and the FP64 GMRES vector kernels -- from x0 = 0 to ||b - A x|| <= 1e-8 ||b||,
 with the problem already set up and b already resident in HBM.  The timed
 form is the production one (FP32 V-cycle inside FP64 FGMRES); the plain FP64
-solve is timed the same way beside it.  The dominant kernel's roofline is
+solve is timed the same way beside it.  The default workload is the 96^3 Q3
+sphere in its stabilised form (see paper_2506_12899_amd/workloads.py); the 2D
+Q2 star's solve times are added as extra keys.  The dominant kernel's roofline is
 measured live with HIP events on the library's stream, and the CPU oracle is
 timed on the host on the same problem.
 
@@ -148,31 +150,87 @@ def copy_probe(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / t / 1e9
 
 
-def cpu_baseline(prob, gpu_its, budget_s=60.0):
-    """The oracle (plain NumPy/SciPy FP64) on the host: full FGMRES solve to 1e-8."""
+def _host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{"api": i.get("internal_api"), "threads": i.get("num_threads")} for i in threadpool_info()]
+    except Exception:  # threadpoolctl missing: leave the BLAS threads unknown
+        pass
+    return model, blas
+
+
+# finest-level operator evaluations per FGMRES iteration of a V(1,1) cycle: the
+# outer w = A z, and per SSOR step four colour updates (each the residual of
+# half the cells) for the pre- and the post-smoothing step, plus the residual
+# before the restriction: 1 + 2 * 2 + 1
+APPLIES_PER_ITERATION = 6
+
+
+def cpu_baseline(prob, gpu_its, budget_s=30.0, max_dofs=2_000_000):
+    """The oracle (plain NumPy/SciPy FP64) on the host.
+
+    Workloads whose hierarchy the oracle can assemble (at most max_dofs): a
+    full FGMRES solve to 1e-8 if it fits the budget, else two oracle
+    iterations scaled to the GPU's iteration count.  Larger workloads (the 3D
+    Q3 ones, whose assembled operator would not fit in host memory): the
+    oracle's per-cell operator (the element blocks of one cell summed, Sec.
+    2.2) on a sample of the finest level's cells, scaled to the whole level and
+    to the finest-level operator evaluations of the GPU solve; this omits the
+    coarser levels, the block solves and the Krylov vectors, so it is a lower
+    bound of the oracle's solve time."""
     import numpy as np
-    from oracle import krylov, mg
+    from oracle import dg, krylov, mg
     from tests.oracle_geom import oracle_geometry
-    H = mg.Hierarchy(oracle_geometry(prob.geometry), prob.dim, prob.n, prob.p)
-    L = H.fine
-    b = L.rhs(prob.solution.f, prob.solution.u)
-    t0 = time.perf_counter()
-    _, its1, _, _, _ = krylov.fgmres(L.apply, H.vcycle, b, tol=1e-8, max_iter=2)
-    t_two = time.perf_counter() - t0
-    per_it = t_two / max(its1, 1)
-    if per_it * max(gpu_its, 1) <= budget_s:
-        t0 = time.perf_counter()
-        _, its, rel, conv, _ = krylov.fgmres(L.apply, H.vcycle, b, tol=1e-8, max_iter=1000)
-        t = time.perf_counter() - t0
-        sample = f"full oracle FGMRES(30) solve of {prob.name} to 1e-8 ({its} iterations, rel {rel:.1e})"
-    else:
-        t = per_it * gpu_its
-        sample = (f"2 oracle FGMRES iterations of {prob.name} ({per_it:.2f} s each), "
-                  f"scaled to the GPU solve's {gpu_its} iterations")
+    model, blas = _host_info()
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    return {"value": t, "unit": "s", "cores": int(threads) if threads.isdigit() else os.cpu_count(),
-            "kind": "oracle", "sample": sample,
+    base = {"unit": "s", "cores": int(threads) if threads.isdigit() else os.cpu_count(), "kind": "oracle",
+            "cpu_model": model, "blas_threads": blas,
             "note": "SciPy BSR mat-vec and the Python loops run on one core; batched block products use BLAS"}
+    lkw = {k: v for k, v in prob.opts.items() if k in ("lambda_frac", "penalty_p", "frac_m", "min_neighbours")}
+    n_cells = prob.n ** prob.dim
+    if n_cells * (prob.p + 1) ** prob.dim / 4 <= max_dofs:
+        H = mg.Hierarchy(oracle_geometry(prob.geometry), prob.dim, prob.n, prob.p, **prob.opts)
+        L = H.fine
+        b = L.rhs(prob.solution.f, prob.solution.u)
+        t0 = time.perf_counter()
+        _, its1, _, _, _ = krylov.fgmres(L.apply, H.vcycle, b, tol=1e-8, max_iter=2)
+        per_it = (time.perf_counter() - t0) / max(its1, 1)
+        if per_it * max(gpu_its, 1) <= budget_s:
+            t0 = time.perf_counter()
+            _, its, rel, conv, _ = krylov.fgmres(L.apply, H.vcycle, b, tol=1e-8, max_iter=1000)
+            t = time.perf_counter() - t0
+            sample = f"full oracle FGMRES(30) solve of {prob.name} to 1e-8 ({its} iterations, rel {rel:.1e})"
+        else:
+            t = per_it * gpu_its
+            sample = (f"2 oracle FGMRES iterations of {prob.name} ({per_it:.2f} s each), "
+                      f"scaled to the GPU solve's {gpu_its} iterations")
+        return dict(base, value=t, sample=sample)
+    L = dg.Level(oracle_geometry(prob.geometry), prob.dim, prob.n, prob.p, build_matrix=False, **lkw)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(L.n_dofs)
+    cells = rng.choice(L.n_act, size=min(L.n_act, 256), replace=False)
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < budget_s and done < len(cells):
+        L.cell_apply(cells[done:done + 32], x)
+        done += min(32, len(cells) - done)
+    per_cell = (time.perf_counter() - t0) / done
+    t = per_cell * L.n_act * APPLIES_PER_ITERATION * max(gpu_its, 1)
+    sample = (f"oracle per-cell operator on {done} sampled cells of {prob.name}'s finest level "
+              f"({per_cell * 1e3:.2f} ms per cell), scaled to {L.n_act} cells x {APPLIES_PER_ITERATION} "
+              f"finest-level applies per iteration x the GPU solve's {gpu_its} iterations (lower bound: "
+              "coarser levels, block solves and Krylov vectors left out)")
+    return dict(base, value=t, sample=sample)
 
 
 def main():
@@ -180,7 +238,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="star512_q2")
+    ap.add_argument("--workload", default="sphere96_q3")
+    ap.add_argument("--extra", default="star512_q2",
+                    help="comma-separated workloads whose solve times are added as extra keys ('' for none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--max-iter", type=int, default=300, help="FGMRES iteration cap (failure beyond it)")
@@ -198,7 +258,7 @@ def main():
 
     prob = workloads.problem(args.workload)
     t0 = time.perf_counter()
-    pb = Problem(prob.geometry, prob.n, prob.p, device=0)
+    pb = Problem(prob.geometry, prob.n, prob.p, device=0, **prob.opts)
     setup_s = time.perf_counter() - t0
     b = pb.rhs(prob.solution.f, prob.solution.u)
     x = torch.empty_like(b)
@@ -258,9 +318,10 @@ def main():
     gbs64 = by64 / ta64 / 1e9
     gbs_s = bs32 / ts32 / 1e9
     # dominant kernel of the timed (FP32 V-cycle) solve: the finest-level colour update,
-    # the largest share of the solve's kernel time of any kernel on one level (about
-    # 16 % on the 2D Q2 star with its FP64-writing form); on the coarser levels the
-    # same kernel is bound by launch latency, not by bandwidth
+    # the largest share of the solve's kernel time of any kernel (on the 96^3 Q3
+    # sphere about a quarter of the FP32 solve, with its FP64-writing form; the
+    # FP64 Gram-Schmidt sweeps come next); on the coarser levels the same kernel
+    # is bound by launch latency, not by bandwidth
     roof = {"bound": "hbm", "kernel": "cellop_kernel<OP_SMOOTH> (finest-level colour update, FP32)",
             "achieved": gbs_s, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs_s / HBM_PEAK_GBS,
             "traffic": counter_traffic(prob.name, "smooth_fp32"), "bytes_per_launch": bs32,
@@ -277,7 +338,8 @@ def main():
         "ms_per_step": t32 * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 V-cycle / f64 Krylov", "data": "synthetic",
         "config": {"workload": prob.name, "dim": prob.dim, "n": prob.n, "p": prob.p, "n_dofs": int(pb.n_dofs),
-                   "solver": "FGMRES(30) + hp-MG V(1,1), red-black cell SSOR", "tol": 1e-8},
+                   "solver": "FGMRES(30) + hp-MG V(1,1), red-black cell SSOR", "tol": 1e-8,
+                   "options": prob.opts},
         "converged": bool(ok),
         "fp32_iterations": st32["iterations"], "fp32_rel_residual": st32["rel_residual"],
         "fp64_plain_s": t64, "fp64_iterations": st64["iterations"], "fp64_rel_residual": st64["rel_residual"],
@@ -291,6 +353,40 @@ def main():
         "roofline": roof,
         "roofline_apply": roof_apply,
     }
+    # the colour update's dense block products (one N x N product per cell of
+    # the colour), the part that could run on the matrix cores: achieved rate
+    # against the FP32 vector peak without packed FP32 (disabled in this
+    # build: 78.6 TFLOP/s) and the dense FP32 matrix peak (157.3 TFLOP/s)
+    nc = (prob.p + 1) ** prob.dim
+    blk_flops = 2.0 * nc * nc * pb.layout.n_active / 2
+    out["smoother_block_gflops"] = blk_flops / ts32 / 1e9
+    out["smoother_block_util_vs_fp32_valu"] = blk_flops / ts32 / 78.6e12
+    out["smoother_block_util_vs_fp32_mfma"] = blk_flops / ts32 / 157.3e12
+    extra = {}
+    for name in [w for w in args.extra.split(",") if w and w != prob.name]:
+        pe = workloads.problem(name)
+        pbe = Problem(pe.geometry, pe.n, pe.p, device=0, **pe.opts)
+        be = pbe.rhs(pe.solution.f, pe.solution.u)
+        xe = torch.empty_like(be)
+        rec = {"n_dofs": int(pbe.n_dofs)}
+        for fp32 in (0, 1):
+            pbe.set_vcycle_fp32(fp32)
+            pbe.solve(be, xe, tol=1e-8, max_iter=args.max_iter)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, ste = pbe.solve(be, xe, tol=1e-8, max_iter=args.max_iter)
+            torch.cuda.synchronize()
+            key = "fp32" if fp32 else "fp64"
+            rec[f"{key}_s"] = (time.perf_counter() - t0) / args.steps
+            rec[f"{key}_iterations"] = ste["iterations"]
+            rec[f"{key}_converged"] = bool(ste["converged"])
+        extra[name] = rec
+        print(f"[bench] extra {name}: FP32 {rec['fp32_s'] * 1e3:.2f} ms, FP64 {rec['fp64_s'] * 1e3:.2f} ms",
+              file=sys.stderr, flush=True)
+        del pbe, be, xe
+    if extra:
+        out["extra_workloads"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, st64["iterations"])
     print(json.dumps(out), flush=True)

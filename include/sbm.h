@@ -181,7 +181,8 @@ int sbm_apply(struct sbm_problem *pb, const void *x_dev, void *y_dev, int fp32);
 int sbm_vcycle(struct sbm_problem *pb, const void *r_dev, void *z_dev, int fp32);
 
 /* Solve A x = b with FGMRES(restart), right-preconditioned by one V-cycle
- * (FP32 if o->vcycle_fp32), FP64 Arnoldi (CGS2), x0 = 0; stops when the TRUE
+ * (FP32 if o->vcycle_fp32), FP64 Arnoldi (classical Gram-Schmidt, second pass
+ * only when the first cancels: |w'| < 0.1 |w|), x0 = 0; stops when the TRUE
  * relative residual ||b - A x|| / ||b|| <= tol, or after max_iter
  * iterations (then SBM_NOT_CONVERGED, x holds the last iterate).  b, x: FP64
  * device vectors.  Synchronous.  st may be NULL. */

@@ -7,8 +7,9 @@
 // cells of one colour do not couple.  Level 0 applies the dense inverse.
 //
 // FGMRES(m) (Sec. 3 opening, GMRES with the V-cycle preconditioner): right
-// preconditioning, x0 = 0, classical Gram-Schmidt with one
-// re-orthogonalisation (CGS2) in FP64 on the device, Givens rotations on the
+// preconditioning, x0 = 0, classical Gram-Schmidt with a selective second
+// pass (taken only when the first one cancels, |w'| < 0.1 |w|: the
+// Daniel-Gragg-Kaufman-Stewart test) in FP64 on the device, Givens rotations on the
 // host (one small device-to-host copy per iteration), stop on the true
 // relative residual.
 #include <algorithm>

@@ -96,6 +96,9 @@ CASES = [
     ("union3_q2_ext1", workloads.eight_balls(0), 8, 2, {"ext": 1}),
     ("union3_q3", workloads.eight_balls(0), 8, 3, {}),
     ("union3_q3_stab", workloads.eight_balls(0), 16, 3, STAB3),
+    # penalty-free variant (Sec. 2.1 remark, Fig. 1 dashed curves): alpha = -1, sigma_Gamma = 0
+    ("disk_q2_penalty_free", workloads.balls([[0.03, -0.02]], [0.7]), 24, 2, {"alpha": -1.0, "c_G": 0.0}),
+    ("sphere_q2_penalty_free", workloads.balls([[0.03, -0.02, 0.01]], [0.75]), 8, 2, {"alpha": -1.0, "c_G": 0.0}),
     # a coarsest level of one to three cells (fewer coarse DoFs than lanes of
     # the coarse-solve kernel's row loop)
     ("small_disk_q2_deep", workloads.balls([[0.25, 0.25]], [0.3]), 16, 2, {"coarse_dofs": 0}),
