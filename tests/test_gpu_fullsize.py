@@ -149,8 +149,10 @@ def _level_opts(prob):
 def _coarser(prob, n, p):
     key = (prob.name, n, p)
     if key not in _LEVELS:
-        _LEVELS[key] = dg.Level(oracle_geometry(prob.geometry), prob.dim, n, p, build_matrix=False,
-                                **_level_opts(prob))
+        kw = _level_opts(prob)
+        if n != prob.n:
+            kw.pop("min_neighbours", None)     # the k-core rule shapes the finest mesh only
+        _LEVELS[key] = dg.Level(oracle_geometry(prob.geometry), prob.dim, n, p, build_matrix=False, **kw)
     return _LEVELS[key]
 
 
