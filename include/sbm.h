@@ -189,6 +189,31 @@ int sbm_vcycle(struct sbm_problem *pb, const void *r_dev, void *z_dev, int fp32)
 int sbm_solve(struct sbm_problem *pb, const double *b_dev, double *x_dev, double tol, int restart,
               int max_iter, sbm_stats *st);
 
+/* Size of the device array that holds the workspace of sbm_solve_noalloc on
+ * each GPU (128 MiB). */
+#define SBM_NOALLOC_SCRATCH_BYTES (128ull << 20)
+
+/* Allocation-free variant of sbm_solve, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, arithmetic and results as
+ * sbm_solve; the FGMRES workspace (Krylov bases, work vector, partial sums,
+ * device scalars) lives in one file-scope device array of
+ * SBM_NOALLOC_SCRATCH_BYTES instead of buffers owned by the problem, and the
+ * call makes no device or host allocation (the problem itself, set up by
+ * sbm_setup, already holds every level's data and the pinned staging word).
+ * Limit: sbm_solve_noalloc_doubles(pb, restart) * 8 must not exceed
+ * SBM_NOALLOC_SCRATCH_BYTES (about 2 (restart + 1) n_dofs doubles; 270k DoFs
+ * at restart 30), else SBM_EINVAL with a message (sbm_last_error) and nothing
+ * runs.  Every problem on one GPU shares that GPU's array, which keeps the
+ * last call's contents (none of it needs to start at zero): calls that overlap
+ * on one GPU -- two streams, two threads -- race and must be serialised by the
+ * caller.  Synchronous, like sbm_solve. */
+int sbm_solve_noalloc(struct sbm_problem *pb, const double *b_dev, double *x_dev, double tol, int restart,
+                      int max_iter, sbm_stats *st);
+/* Doubles of scratch the allocation-free solve needs for pb at this restart
+ * length (-1 for an invalid problem or restart).  Host only. */
+long long sbm_solve_noalloc_doubles(const struct sbm_problem *pb, int restart);
+
 /* Switch the precision of the V-cycle used by later sbm_solve calls
  * (0 = FP64, 1 = FP32 with FP32 blocks; the outer Arnoldi, the operator in
  * the Krylov space, the true residual and x stay FP64).  Host only. */

@@ -14,6 +14,7 @@
 // relative residual.
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -866,24 +867,29 @@ int sbm_sync(sbm_problem *pb) {
     return SBM_OK;
 }
 
-static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st) {
-    if (!pb || pb->host_only || !b || !x || b == x || m < 1 || m > 30 || max_iter < 1 || !(tol > 0)) return SBM_EINVAL;
+// FGMRES workspace: the Krylov bases V ((m+1) x n) and Z (m x n), the work
+// vector w (n), two partial-sum buffers (2 gs_partials_max) and 128 doubles
+// of device scalars.  None of it needs to start at zero: every entry is
+// written before it is read.
+struct SolveWork {
+    double *V = nullptr, *Z = nullptr, *w = nullptr, *red = nullptr, *hdev = nullptr;
+};
+
+static constexpr int MAX_RESTART = 30;
+
+static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st,
+                      const SolveWork &ws) {
+    if (!pb || pb->host_only || !b || !x || b == x || m < 1 || m > MAX_RESTART || max_iter < 1 || !(tol > 0))
+        return SBM_EINVAL;
     auto t0 = std::chrono::steady_clock::now();
     const HostLevel &L = pb->levels.back();
     const long long n = (long long)L.n_act * L.nc;
     const int lf = (int)pb->levels.size() - 1;
     hipStream_t s = pb->stream;
     int rc;
-    if (pb->ws_restart < m) {
-        if ((rc = dalloc(pb, &pb->V, (size_t)(m + 1) * n)) || (rc = dalloc(pb, &pb->Z, (size_t)m * n)) ||
-            (rc = dalloc(pb, &pb->w, (size_t)n)) || (rc = dalloc(pb, &pb->red, (size_t)2 * sbm::gs_partials_max())) ||
-            (rc = dalloc(pb, &pb->hdev, (size_t)128)))
-            return rc;
-        pb->ws_restart = m;
-    }
-    double *V = pb->V, *Z = pb->Z, *w = pb->w, *hd = pb->hdev, *hp = pb->pinned;
+    double *V = ws.V, *Z = ws.Z, *w = ws.w, *hd = ws.hdev, *hp = pb->pinned;
     // two partial-sum buffers: the passes of one Arnoldi step alternate between them
-    double *pa = pb->red, *pq = pb->red + sbm::gs_partials_max();
+    double *pa = ws.red, *pq = ws.red + sbm::gs_partials_max();
     const bool f32 = pb->opt.vcycle_fp32 != 0;
     // ||b||
     KCHK(launch_gs_dots(n, 0, nullptr, b, pa, s));
@@ -900,7 +906,10 @@ static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, i
         HIPCHK(hipStreamSynchronize(s));
         return SBM_OK;
     }
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+    // Hessenberg matrix, Givens rotations and the reduced right-hand side on
+    // the stack (m <= MAX_RESTART): the solve allocates nothing on the host
+    double H[(MAX_RESTART + 1) * MAX_RESTART], cs[MAX_RESTART], sn[MAX_RESTART], gv[MAX_RESTART + 1],
+        y[MAX_RESTART];
     // r = b (x0 = 0); v0 = r / ||r||
     HIPCHK(hipMemcpyAsync(w, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     double beta = nb;
@@ -913,8 +922,8 @@ static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, i
         // 127 beta^2
         HIPCHK(hipMemcpyAsync(hd + 127, hp, sizeof(double), hipMemcpyHostToDevice, s));
         KCHK(launch_scale(n, hd + 127, w, V, s));
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(gv.begin(), gv.end(), 0.0);
+        std::fill(H, H + (size_t)(m + 1) * m, 0.0);
+        std::fill(gv, gv + m + 1, 0.0);
         gv[0] = beta;
         int j = 0;
         bool est_ok = false;
@@ -1048,7 +1057,104 @@ static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, i
 // (host containers throw std::bad_alloc; nothing may leave through the C ABI)
 int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st) {
     try {
-        return solve_body(pb, b, x, tol, m, max_iter, st);
+        if (!pb || pb->host_only || m < 1 || m > MAX_RESTART) return SBM_EINVAL;
+        const HostLevel &L = pb->levels.back();
+        const long long n = (long long)L.n_act * L.nc;
+        int rc;
+        if (pb->ws_restart < m) {
+            if ((rc = dalloc(pb, &pb->V, (size_t)(m + 1) * n)) || (rc = dalloc(pb, &pb->Z, (size_t)m * n)) ||
+                (rc = dalloc(pb, &pb->w, (size_t)n)) ||
+                (rc = dalloc(pb, &pb->red, (size_t)2 * sbm::gs_partials_max())) ||
+                (rc = dalloc(pb, &pb->hdev, (size_t)128)))
+                return rc;
+            pb->ws_restart = m;
+        }
+        SolveWork ws;
+        ws.V = pb->V;
+        ws.Z = pb->Z;
+        ws.w = pb->w;
+        ws.red = pb->red;
+        ws.hdev = pb->hdev;
+        return solve_body(pb, b, x, tol, m, max_iter, st, ws);
+    } catch (const std::bad_alloc &) {
+        return SBM_ENOMEM;
+    } catch (...) {
+        return SBM_EINVAL;
+    }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve.  The FGMRES workspace lives in one file-scope device
+// array of SBM_NOALLOC_SCRATCH_BYTES, which every GPU the library runs on
+// holds from the module's load until the process ends.  In host code the
+// array's name only stands for the device symbol: its device address is
+// looked up once per device (with that device current) and kept, and only
+// that address ever reaches a kernel or a copy.
+static __device__ __align__(256) double scratch[SBM_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+static constexpr int MAX_DEVICES = 64;
+static double *scratch_dev[MAX_DEVICES];
+static std::mutex scratch_mutex;
+
+static int scratch_address(sbm_problem *pb, double **out) {
+    const int dev = pb->opt.device;
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        pb->last_error = "device ordinal out of range for the allocation-free solve";
+        return SBM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (scratch_dev[dev] == nullptr) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || (cur != dev && hipSetDevice(dev) != hipSuccess)) return SBM_EDEVICE;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) hipSetDevice(cur);
+        if (e != hipSuccess || p == nullptr) {
+            pb->last_error = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+            return SBM_EDEVICE;
+        }
+        scratch_dev[dev] = (double *)p;
+    }
+    *out = scratch_dev[dev];
+    return SBM_OK;
+}
+
+extern "C" {
+
+long long sbm_solve_noalloc_doubles(const sbm_problem *pb, int m) {
+    if (!pb || pb->host_only || m < 1 || m > MAX_RESTART) return -1;
+    const HostLevel &L = pb->levels.back();
+    const long long n = (long long)L.n_act * L.nc;
+    auto up = [](long long k) { return (k + 31) / 32 * 32; };   // 256-byte sections
+    return up((long long)(m + 1) * n) + up((long long)m * n) + up(n) + up(2LL * sbm::gs_partials_max()) + up(128);
+}
+
+int sbm_solve_noalloc(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st) {
+    try {
+        if (!pb || pb->host_only || m < 1 || m > MAX_RESTART) return SBM_EINVAL;
+        const long long need = sbm_solve_noalloc_doubles(pb, m);
+        const long long cap = (long long)(SBM_NOALLOC_SCRATCH_BYTES / sizeof(double));
+        if (need > cap) {
+            pb->last_error = "allocation-free solve: the FGMRES(" + std::to_string(m) + ") workspace needs " +
+                             std::to_string(need * 8) + " bytes, the scratch array holds " +
+                             std::to_string(cap * 8) + " (fewer DoFs or a shorter restart)";
+            return SBM_EINVAL;
+        }
+        double *base = nullptr;
+        int rc;
+        if ((rc = scratch_address(pb, &base))) return rc;
+        const HostLevel &L = pb->levels.back();
+        const long long n = (long long)L.n_act * L.nc;
+        auto up = [](long long k) { return (k + 31) / 32 * 32; };
+        SolveWork ws;
+        ws.V = base;
+        ws.Z = ws.V + up((long long)(m + 1) * n);
+        ws.w = ws.Z + up((long long)m * n);
+        ws.red = ws.w + up(n);
+        ws.hdev = ws.red + up(2LL * sbm::gs_partials_max());
+        return solve_body(pb, b, x, tol, m, max_iter, st, ws);
     } catch (const std::bad_alloc &) {
         return SBM_ENOMEM;
     } catch (...) {

@@ -14,6 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libsbm.so")
 
 SBM_OK, SBM_NOT_CONVERGED = 0, 1
+SBM_EINVAL = -1
+NOALLOC_SCRATCH_BYTES = 128 << 20     # SBM_NOALLOC_SCRATCH_BYTES in include/sbm.h
 GEOM_BALLS, GEOM_STAR2D, GEOM_CALLBACK, GEOM_ELLIPSOID = 0, 1, 2, 3
 
 PHI_FN = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.c_void_p)
@@ -65,6 +67,8 @@ SIGNATURES = [
     ("sbm_apply", C.c_int, [_VP, _VP, _VP, C.c_int]),
     ("sbm_vcycle", C.c_int, [_VP, _VP, _VP, C.c_int]),
     ("sbm_solve", C.c_int, [_VP, _VP, _VP, C.c_double, C.c_int, C.c_int, C.POINTER(Stats)]),
+    ("sbm_solve_noalloc", C.c_int, [_VP, _VP, _VP, C.c_double, C.c_int, C.c_int, C.POINTER(Stats)]),
+    ("sbm_solve_noalloc_doubles", C.c_longlong, [_VP, C.c_int]),
     ("sbm_level_apply", C.c_int, [_VP, C.c_int, _VP, _VP, C.c_int]),
     ("sbm_colour_update", C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP, C.c_int]),
     ("sbm_restrict", C.c_int, [_VP, C.c_int, _VP, _VP, C.c_int]),

@@ -224,12 +224,16 @@ class Problem:
     def set_vcycle_fp32(self, fp32):
         N.check(N.lib().sbm_set_vcycle_fp32(self._h, int(bool(fp32))), self._h)
 
-    def solve(self, b, x=None, tol=1e-8, restart=30, max_iter=1000, vcycle_fp32=None):
+    def solve(self, b, x=None, tol=1e-8, restart=30, max_iter=1000, vcycle_fp32=None, noalloc=False):
+        """FGMRES solve (sbm_solve); noalloc=True takes the allocation-free
+        entry point (sbm_solve_noalloc: workspace in the library's fixed
+        device scratch array)."""
         if vcycle_fp32 is not None:
             self.set_vcycle_fp32(vcycle_fp32)
         x = torch.empty_like(b) if x is None else x
         self._vectors((b, -1), (x, -1), dtype=torch.float64)
         st = N.Stats()
-        status = N.check(N.lib().sbm_solve(self._h, _ptr(b), _ptr(x), tol, restart, max_iter, C.byref(st)), self._h)
+        fn = N.lib().sbm_solve_noalloc if noalloc else N.lib().sbm_solve
+        status = N.check(fn(self._h, _ptr(b), _ptr(x), tol, restart, max_iter, C.byref(st)), self._h)
         return x, dict(status=status, iterations=st.iterations, converged=bool(st.converged),
                        rel_residual=st.rel_residual_true, seconds=st.seconds)
