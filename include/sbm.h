@@ -287,6 +287,20 @@ int sbm_boundary_cells(const struct sbm_problem *pb, int *n_boundary, int *cells
 int sbm_boundary_features(const struct sbm_problem *pb, double *host_out, long long cap);
 int sbm_boundary_samples(struct sbm_problem *pb, const double *r_dev, const double *e_dev, double *R_dev,
                          double *BR_dev, double *E_dev);
+/* Training pairs of the boundary cells from the method's own iterates (device,
+ * FP64, asynchronous): for a known discrete solution x* (b = A x*) and an
+ * iterate z, r = b - A z on the finest level, then per boundary cell K (in
+ * sbm_boundary_cells order) R = r_K, BR = B_K r_K, E = x*_K - z_K, each row
+ * triple scaled by 1 / |E| (the loss is invariant to a per-sample scale);
+ * valid[b] = 0 and zero rows where |E| = 0 or an entry is not finite.
+ * R, BR, E: n_boundary x (p+1)^d; valid: n_boundary ints.  Uses two
+ * finest-level work vectors the problem allocates on first use. */
+int sbm_collect_pairs(struct sbm_problem *pb, const double *x_star_dev, const double *b_dev, const double *z_dev,
+                      double *R_dev, double *BR_dev, double *E_dev, int *valid_dev);
+/* steps preconditioned Richardson iterations z <- z + M^{-1}(b - A z) with the
+ * FP64 V-cycle (Sec. 3 smoother and cycle; the learned correction when it is
+ * switched on), finest level, in place (device, asynchronous). */
+int sbm_richardson(struct sbm_problem *pb, const double *b_dev, double *z_dev, int steps);
 int sbm_set_learned(struct sbm_problem *pb, const float *params_dev, int width);
 int sbm_set_learned_arrays(struct sbm_problem *pb, const double *w, const double *U, const double *V);
 int sbm_use_learned(struct sbm_problem *pb, int on);

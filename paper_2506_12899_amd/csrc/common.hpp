@@ -160,4 +160,6 @@ struct sbm_problem {
     int learned_nout = 0;
     float *lrn_X = nullptr, *lrn_O = nullptr;
     short *lrn_wbuf = nullptr;
+    // finest-level work vectors of the training-data entry points (allocated on first use)
+    double *pair_r = nullptr, *pair_t = nullptr;
 };

@@ -1,5 +1,6 @@
 // C ABI of the learned boundary-cell correction (features, training kernels,
 // BF16 inference and installation into the smoother).  See mlp.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -79,9 +80,105 @@ void features(const sbm_problem *pb, std::vector<double> &F) {
     }
 }
 
+// One block per finest-level boundary cell K: R = r_K, BR = B_K r_K,
+// E = x*_K - z_K, all three scaled by 1 / |E| (the loss is invariant to a
+// per-sample scale); valid = 0 (and the rows zero) when |E| = 0 or any entry
+// is not finite.
+__global__ __launch_bounds__(64) void collect_pairs_kernel(int nc, const int *__restrict__ bnd_cells,
+                                                           const double *__restrict__ Bt, const double *__restrict__ r,
+                                                           const double *__restrict__ xs,
+                                                           const double *__restrict__ z, double *__restrict__ R,
+                                                           double *__restrict__ BR, double *__restrict__ E,
+                                                           int *__restrict__ valid) {
+    __shared__ double rs[64], e2[64];
+    __shared__ int ok;
+    const int b = blockIdx.x, i = threadIdx.x;
+    const int K = bnd_cells[b];
+    double ri = 0, ei = 0;
+    if (i < nc) {
+        ri = r[(size_t)K * nc + i];
+        ei = xs[(size_t)K * nc + i] - z[(size_t)K * nc + i];
+    }
+    rs[i] = ri;
+    e2[i] = ei * ei;
+    if (i == 0) ok = 1;
+    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+        if (i < off) e2[i] += e2[i + off];
+        __syncthreads();
+    }
+    double acc = 0;
+    if (i < nc) {
+        const double *B = Bt + (size_t)b * nc * nc;
+        for (int j = 0; j < nc; ++j) acc += B[(size_t)j * nc + i] * rs[j];
+    }
+    const double n2 = e2[0];
+    if (!std::isfinite(ri) || !std::isfinite(acc) || !std::isfinite(ei) || !(n2 > 0) || !std::isfinite(n2)) ok = 0;
+    __syncthreads();
+    const double sc = ok ? 1.0 / std::sqrt(n2) : 0.0;
+    if (i < nc) {
+        R[(size_t)b * nc + i] = ri * sc;
+        BR[(size_t)b * nc + i] = acc * sc;
+        E[(size_t)b * nc + i] = ei * sc;
+    }
+    if (i == 0) valid[b] = ok;
+}
+
+__global__ void axpy_kernel(long long n, const double *__restrict__ t, double *__restrict__ z) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) z[i] += t[i];
+}
+
+int pair_vectors(sbm_problem *pb) {
+    if (pb->pair_r) return SBM_OK;
+    const HostLevel &L = pb->levels.back();
+    const size_t n = (size_t)L.n_act * L.nc;
+    int rc;
+    if ((rc = lalloc(pb, &pb->pair_r, n)) || (rc = lalloc(pb, &pb->pair_t, n))) return rc;
+    return SBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int sbm_collect_pairs(sbm_problem *pb, const double *x_star, const double *b, const double *z, double *R, double *BR,
+                      double *E, int *valid) {
+    if (!pb || pb->host_only || !x_star || !b || !z || !R || !BR || !E || !valid) return SBM_EINVAL;
+    int rc;
+    if ((rc = pair_vectors(pb))) return rc;
+    if ((rc = finest_residual(pb, z, b, pb->pair_r))) return rc;
+    auto &D = pb->dev64.back();
+    if (D.n_bnd == 0) return SBM_OK;
+    if (D.nc > 64) return SBM_EINVAL;
+    hipLaunchKernelGGL(collect_pairs_kernel, dim3(D.n_bnd), dim3(64), 0, pb->stream, D.nc, D.bnd_cells, D.Bbnd_t,
+                       pb->pair_r, x_star, z, R, BR, E, valid);
+    if (hipGetLastError() != hipSuccess) {
+        pb->last_error = "collect_pairs launch failed";
+        return SBM_EDEVICE;
+    }
+    return SBM_OK;
+}
+
+int sbm_richardson(sbm_problem *pb, const double *b, double *z, int steps) {
+    if (!pb || pb->host_only || !b || !z || b == z || steps < 0) return SBM_EINVAL;
+    int rc;
+    if ((rc = pair_vectors(pb))) return rc;
+    const HostLevel &L = pb->levels.back();
+    const long long n = (long long)L.n_act * L.nc;
+    for (int s = 0; s < steps; ++s) {
+        if ((rc = finest_residual(pb, z, b, pb->pair_r))) return rc;
+        if ((rc = sbm_vcycle(pb, pb->pair_r, pb->pair_t, 0))) return rc;
+        const int nbk = (int)std::min<long long>((n + 255) / 256, 8192);
+        hipLaunchKernelGGL(axpy_kernel, dim3(nbk), dim3(256), 0, pb->stream, n, pb->pair_t, z);
+        if (hipGetLastError() != hipSuccess) {
+            pb->last_error = "richardson update launch failed";
+            return SBM_EDEVICE;
+        }
+    }
+    return SBM_OK;
+}
 
 int sbm_feature_dim(int dim) { return (dim == 2 || dim == 3) ? feature_dim(dim) : SBM_EINVAL; }
 

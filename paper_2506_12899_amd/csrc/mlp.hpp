@@ -25,4 +25,7 @@ int launch_boundary_samples(int nb, int nc, const int *bnd_cells, const double *
 
 inline int feature_dim(int d) { return 2 * d * (4 + 2 * d); }
 
+// r = b - A x on the finest level, FP64 (solver.hip)
+int finest_residual(sbm_problem *pb, const double *x, const double *b, double *r);
+
 }  // namespace sbm

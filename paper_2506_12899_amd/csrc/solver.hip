@@ -415,6 +415,12 @@ int check_level(sbm_problem *pb, int &level) {
 
 }  // namespace
 
+namespace sbm {
+int finest_residual(sbm_problem *pb, const double *x, const double *b, double *r) {
+    return level_apply<double>(pb, (int)pb->levels.size() - 1, OP_RESID, x, r, b);
+}
+}  // namespace sbm
+
 extern "C" {
 
 const char *sbm_strerror(int s) {

@@ -6,12 +6,13 @@ trained with the library's forward, loss, backward and Adam kernels; inference
 runs through sbm_set_learned (BF16 on the matrix cores).  Torch provides device
 memory only.
 
-Data protocol (per seeded training geometry, p = 3, 3D): x* ~ N(0, 1), b = A x*,
-z = 0 (a white-noise error, the part a smoother must remove); before each
-finest-level colour update of the pre-smoothing step the boundary cells of
-that colour contribute the pair (e_K = x*_K - z_K, r_K = (b - A z)_K)
-together with B_K r_K and the cell's features; optional further outer
-iterations continue with z += V-cycle(b - A z).
+Data protocol (per seeded training geometry, p = 3, 3D): x* ~ N(0, 1), b = A x*;
+from z = 0 and from the iterates after a few preconditioned Richardson steps
+z += V-cycle(b - A z) (where the error modes the plain cycle handles badly
+dominate), before each finest-level colour update of one smoothing step the
+boundary cells of that colour contribute the pair (e_K = x*_K - z_K,
+r_K = (b - A z)_K) together with B_K r_K and the cell's features, scaled to
+|e_K| = 1 (sbm_collect_pairs, sbm_richardson).
 
 Checkpoint format (little-endian): magic b"SBMMLP01", int32 n_in, width,
 n_out, n_cell, int64 step, then params, Adam m, Adam v as float32.
@@ -153,16 +154,40 @@ def boundary_samples(pb, r, e):
     return R, BR, E
 
 
-def generate(problem_factory, seeds, n, p=3, outer=1, draws=4, device="cuda", log=print):
-    """Training samples from the method's own smoothing on seeded geometries.
+def collect_pairs(pb, xs, b, z):
+    """(R, BR, E, valid) of every finest-level boundary cell for the iterate z
+    (sbm_collect_pairs: residual, error, block product and the per-sample
+    normalisation |E| = 1 run in the library)."""
+    nb = pb.layout.n_boundary_cells
+    nc = pb.layout.dofs_per_cell
+    R = torch.empty(nb, nc, dtype=torch.float64, device=b.device)
+    BR, E = torch.empty_like(R), torch.empty_like(R)
+    valid = torch.empty(nb, dtype=torch.int32, device=b.device)
+    N.check(N.lib().sbm_collect_pairs(pb._h, _p(xs), _p(b), _p(z), _p(R), _p(BR), _p(E), _p(valid)), pb._h)
+    return R, BR, E, valid
 
-    For each geometry, `draws` random exact solutions x* (white-noise initial
-    error) and `outer` outer iterations; before each finest-level colour
-    update of the pre-smoothing step the boundary cells of that colour give a
-    sample."""
+
+def richardson(pb, b, z, steps):
+    """z <- z + V-cycle(b - A z), `steps` times, in the library."""
+    if steps > 0:
+        N.check(N.lib().sbm_richardson(pb._h, _p(b), _p(z), int(steps)), pb._h)
+
+
+def generate(problem_factory, seeds, n, p=3, iterates=(0,), draws=4, device="cuda", log=print, geometry=None):
+    """Training samples from the method's own iterations on seeded geometries.
+
+    For each geometry (workloads.training_geometry(seed), or geometry(seed)),
+    `draws` random discrete solutions x* (b = A x*), and for each count k in
+    `iterates` the iterate z after k preconditioned Richardson steps from
+    z = 0 (k = 0: white-noise error; larger k: the error modes the V-cycle
+    reduces slowly dominate); from that iterate one smoothing step (colours 0,
+    1, 1, 0) runs, and before each finest-level colour update the boundary
+    cells of that colour give a pair (e_K, r_K) with B_K r_K and the cell's
+    features.  Every piece of the method's arithmetic runs in the library;
+    torch selects rows and concatenates."""
     Xs, Rs, BRs, Es = [], [], [], []
     for s in seeds:
-        geo = workloads.training_geometry(s)
+        geo = workloads.training_geometry(s) if geometry is None else geometry(s)
         pb = problem_factory(geo, n, p)
         cells, F = boundary_info(pb)
         if len(cells) == 0:
@@ -177,23 +202,19 @@ def generate(problem_factory, seeds, n, p=3, outer=1, draws=4, device="cuda", lo
             xs = torch.randn(pb.n_dofs, dtype=torch.float64, generator=g).to(device)
             b = pb.apply(xs)
             z = torch.zeros_like(b)
-            for it in range(outer):
+            done = 0
+            for k in sorted(iterates):
+                richardson(pb, b, z, k - done)
+                done = k
+                zz = z.clone()
                 for c in (0, 1, 1, 0):
-                    r = b - pb.apply(z)
-                    R, BR, E = boundary_samples(pb, r, xs - z)
-                    # the loss is invariant to a per-sample scale of (r, B r, e): scale
-                    # each sample to |e| = 1 in FP64 before it is stored in FP32
-                    ne = torch.linalg.vector_norm(E, dim=1)
-                    ok = torch.isfinite(ne) & (ne > 0) & torch.isfinite(R).all(1) & torch.isfinite(BR).all(1)
-                    sel = (col == c) & ok
-                    sc = 1.0 / ne[sel, None]
+                    R, BR, E, valid = collect_pairs(pb, xs, b, zz)
+                    sel = (col == c) & (valid != 0)
                     Xs.append(Ft[sel])
-                    Rs.append(R[sel] * sc)
-                    BRs.append(BR[sel] * sc)
-                    Es.append(E[sel] * sc)
-                    pb.colour_update(lf, c, b, z)
-                if it + 1 < outer:
-                    z = z + pb.vcycle(b - pb.apply(z))
+                    Rs.append(R[sel])
+                    BRs.append(BR[sel])
+                    Es.append(E[sel])
+                    pb.colour_update(lf, c, b, zz)
         pb.close()
         log(f"[learned] geometry {s}: {len(cells)} boundary cells")
     return (torch.cat(Xs).float(), torch.cat(Rs).float(), torch.cat(BRs).float(), torch.cat(Es).float())

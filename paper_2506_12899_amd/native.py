@@ -80,6 +80,8 @@ SIGNATURES = [
     ("sbm_boundary_cells", C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_longlong]),
     ("sbm_boundary_features", C.c_int, [_VP, C.POINTER(C.c_double), C.c_longlong]),
     ("sbm_boundary_samples", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    ("sbm_collect_pairs", C.c_int, [_VP] * 8),
+    ("sbm_richardson", C.c_int, [_VP, _VP, _VP, C.c_int]),
     ("sbm_set_learned", C.c_int, [_VP, _VP, C.c_int]),
     ("sbm_set_learned_arrays", C.c_int, [_VP] + [C.POINTER(C.c_double)] * 3),
     ("sbm_use_learned", C.c_int, [_VP, C.c_int]),

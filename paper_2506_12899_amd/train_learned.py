@@ -26,10 +26,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def judge(net, cases, max_iter=300, tol=1e-8):
+def judge(net, cases, max_iter=300, tol=1e-8, opts=None):
     out = []
     for name, geo, n, sol in cases:
-        pb = Problem(geo, n, 3, device=0)
+        pb = Problem(geo, n, 3, device=0, **(opts or {}))
         b = pb.rhs(sol.f, sol.u)
         learned.use(pb, False)
         _, st0 = pb.solve(b, tol=tol, max_iter=max_iter)
@@ -46,37 +46,42 @@ def judge(net, cases, max_iter=300, tol=1e-8):
     return out
 
 
-def held_out_cases(sizes):
+def held_out_cases(sphere_sizes, union_sizes):
+    """The sphere of the 96^3 workload and the eight-ball union of the 128^3
+    one (neither among the training geometries) at the given sizes."""
     sph = workloads.problem("sphere96_q3")
     uni = workloads.problem("balls128_q3")
-    cases = []
-    for n in sizes:
-        cases.append(("sphere r=0.8", sph.geometry, n, sph.solution))
-        cases.append(("8-ball union", uni.geometry, n, uni.solution))
-    return cases
+    return ([("sphere r=0.8", sph.geometry, n, sph.solution) for n in sphere_sizes] +
+            [("8-ball union", uni.geometry, n, uni.solution) for n in union_sizes])
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
     ap.add_argument("--geometries", type=int, default=200)
-    ap.add_argument("--n", type=int, default=16)
-    ap.add_argument("--outer", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--iterates", default="0,3,8", help="Richardson steps before each sampled smoothing step")
+    ap.add_argument("--plain-form", action="store_true",
+                    help="centre rule and per-level penalties instead of the stabilised 3D Q3 form")
     ap.add_argument("--draws", type=int, default=4)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--judge-sizes", default="16,24,32")
+    ap.add_argument("--judge-sphere", default="32,48,96")
+    ap.add_argument("--judge-union", default="32,64,128")
     ap.add_argument("--time-budget", type=float, default=240.0)
     ap.add_argument("--train-uv", type=int, default=1, help="1: train w, U, V; 0: relaxation weight only")
     args = ap.parse_args()
     dev = torch.device("cuda", 0)
     t0 = time.time()
 
-    def factory(geo, n, p):
-        return Problem(geo, n, p, device=0)
+    opts = {} if args.plain_form else dict(workloads.STABILISED_Q3)
 
-    data = learned.generate(factory, range(1, args.geometries + 1), args.n, 3, args.outer, args.draws, device=dev,
+    def factory(geo, n, p):
+        return Problem(geo, n, p, device=0, **opts)
+
+    its = tuple(int(k) for k in args.iterates.split(","))
+    data = learned.generate(factory, range(1, args.geometries + 1), args.n, 3, its, args.draws, device=dev,
                             log=lambda m: None)
     t_data = time.time() - t0
     log(f"[train] {data[0].shape[0]} samples from {args.geometries} geometries in {t_data:.1f} s")
@@ -87,8 +92,8 @@ def main():
     torch.cuda.synchronize()
     t_train = time.time() - t1
     net.save(args.out)
-    sizes = [int(s) for s in args.judge_sizes.split(",") if s]
-    res = judge(net, held_out_cases(sizes))
+    sz = lambda a: [int(v) for v in a.split(",") if v]  # noqa: E731
+    res = judge(net, held_out_cases(sz(args.judge_sphere), sz(args.judge_union)), opts=opts)
     print(json.dumps(dict(samples=int(data[0].shape[0]), geometries=args.geometries, n_train=args.n,
                           data_s=t_data, train_s=t_train, epochs=len(hist), loss_first=hist[0], loss_last=hist[-1],
                           loss_history=hist, judge=res)), flush=True)

@@ -193,3 +193,43 @@ def test_features_and_samples_match_oracle(pair):
     BRo = np.einsum('kij,kj->ki', H.inv[-1][cells], rr)
     # the two independent FP64 LU inverses agree to ~1e-12 on these blocks
     assert _rel(BR.cpu().numpy(), BRo) <= 1e-10
+
+
+def test_collect_pairs_and_richardson_match_oracle():
+    """sbm_richardson: z after k steps z += V(b - A z) equals the oracle's
+    iterates; sbm_collect_pairs on that iterate: r_K, B_K r_K and e_K =
+    x*_K - z_K of every boundary cell, scaled by 1 / |e_K| (the stabilised
+    3D Q3 form on the 12^3 sphere)."""
+    from paper_2506_12899_amd.learned import boundary_info, collect_pairs, richardson
+    from paper_2506_12899_amd.problem import Problem
+    dev = _dev()
+    geo = workloads.balls([[0.03, -0.02, 0.01]], [0.8])
+    kw = dict(workloads.STABILISED_Q3)
+    pb = Problem(geo, 12, 3, device=0, **kw)
+    H = mg.Hierarchy(oracle_geometry(geo), 3, 12, 3, **kw)
+    L = H.fine
+    xs = workloads.random_vector(L.n_dofs, seed=16)
+    b = L.A @ xs
+    z = np.zeros(L.n_dofs)
+    for _ in range(3):
+        z = z + H.vcycle(b - L.A @ z)
+    bt = torch.from_numpy(b).to(dev)
+    zt = torch.zeros_like(bt)
+    richardson(pb, bt, zt, 3)
+    assert _rel(zt.cpu().numpy(), z) <= 1e-10
+    cells, _ = boundary_info(pb)
+    R, BR, E, valid = collect_pairs(pb, torch.from_numpy(xs).to(dev), bt, zt)
+    assert valid.cpu().numpy().all()
+    zn = zt.cpu().numpy()
+    r = (b - L.A @ zn).reshape(L.n_act, L.N)[cells]
+    e = (xs - zn).reshape(L.n_act, L.N)[cells]
+    sc = 1.0 / np.linalg.norm(e, axis=1, keepdims=True)
+    assert _rel(E.cpu().numpy(), e * sc) <= 1e-12
+    assert _rel(R.cpu().numpy(), r * sc) <= 1e-9       # r ~ 1e-3 |b| after three cycles
+    BRo = np.einsum('kij,kj->ki', H.inv[-1][cells], r) * sc
+    assert _rel(BR.cpu().numpy(), BRo) <= 1e-9
+    # a cell whose error is zero gives an invalid (zero) sample
+    zt2 = torch.from_numpy(xs).to(dev).clone()
+    R2, BR2, E2, valid2 = collect_pairs(pb, torch.from_numpy(xs).to(dev), bt, zt2)
+    assert not valid2.cpu().numpy().any()
+    assert float(E2.abs().max()) == 0.0 and float(R2.abs().max()) == 0.0
