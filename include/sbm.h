@@ -161,6 +161,17 @@ int sbm_level_info(const struct sbm_problem *pb, int level, int *n, int *p, int 
                    int *n_colour0, int *n_surrogate_faces);
 int sbm_shifts(const struct sbm_problem *pb, int level, double *host_out, long long cap);
 
+/* Test hook: replace the shifts d of a level's surrogate Gauss points by
+ * externally supplied ones (host, count = n_surrogate_faces x (p_l+1)^(dim-1)
+ * x dim doubles, physical units, the layout of sbm_shifts), so that kernel
+ * parity can be checked independently of the closest-point search (Sec. 4.2).
+ * The level's boundary-cell blocks and inverses (and, on level 0, the dense
+ * coarse inverse) are rebuilt from them and the device copies of the shifts and
+ * inverses overwritten in place (no allocation).  An installed learned
+ * correction keeps its w, U, V.  Synchronous.  SBM_EINVAL for a wrong count or
+ * non-finite values; on an error the problem keeps its previous shifts. */
+int sbm_set_shifts(struct sbm_problem *pb, int level, const double *host_shifts, long long count);
+
 /* Right-hand side of the DG-SBM system (Sec. 2.2): int_K f phi_i plus, on
  * surrogate faces, [-alpha grad phi_i . n~ + sigma_Gamma phi_i] g(x~ + d).
  * f and g are batched host callbacks: called with npts points (npts x dim,

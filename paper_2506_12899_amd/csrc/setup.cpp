@@ -512,6 +512,11 @@ int build_level(const Geometry &g, const sbm_options &o, int n, int p, bool fine
         }
     }
     L.n_bnd = (int)L.bnd_cells.size();
+    return build_blocks(L, o, err);
+}
+
+int build_blocks(HostLevel &L, const sbm_options &o, std::string &err) {
+    const int d = L.d;
     // blocks and inverses
     const int nc = L.nc;
     const double reg = o.allow_singular ? 1e-10 : 0.0;

@@ -415,6 +415,28 @@ int check_level(sbm_problem *pb, int &level) {
 
 }  // namespace
 
+template <typename T>
+int refresh_level(sbm_problem *pb, const HostLevel &L, DevLevel<T> &D) {
+    const int nc = L.nc;
+    if (L.n_surr) {
+        std::vector<T> sh(L.shifts.size());
+        for (size_t i = 0; i < sh.size(); ++i) sh[i] = (T)(L.shifts[i] / L.h);
+        HIPCHK(hipMemcpy(D.shift, sh.data(), sh.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+    const size_t tot = (size_t)L.n_bnd * nc * nc;
+    if (tot) {
+        std::vector<T> tmp(tot);
+        for (int b = 0; b < L.n_bnd; ++b) {
+            const double *B = &L.Bbnd[(size_t)b * nc * nc];
+            T *o = &tmp[(size_t)b * nc * nc];
+            for (int i = 0; i < nc; ++i)
+                for (int j = 0; j < nc; ++j) o[(size_t)j * nc + i] = (T)B[(size_t)i * nc + j];
+        }
+        HIPCHK(hipMemcpy(D.Bbnd_t, tmp.data(), tot * sizeof(T), hipMemcpyHostToDevice));
+    }
+    return SBM_OK;
+}
+
 namespace sbm {
 int finest_residual(sbm_problem *pb, const double *x, const double *b, double *r) {
     return level_apply<double>(pb, (int)pb->levels.size() - 1, OP_RESID, x, r, b);
@@ -833,6 +855,65 @@ int sbm_vcycle(sbm_problem *pb, const void *r, void *z, int fp32) {
     int l = (int)pb->levels.size() - 1;
     return fp32 ? vcycle_rec<float>(pb, l, (const float *)r, (float *)z)
                 : vcycle_rec<double>(pb, l, (const double *)r, (double *)z);
+}
+
+static int set_shifts_body(sbm_problem *pb, int level, const double *shifts, long long count) {
+    if (!pb || !shifts) return SBM_EINVAL;
+    const int nl = (int)pb->levels.size();
+    if (level == -1) level = nl - 1;
+    if (level < 0 || level >= nl) return SBM_EINVAL;
+    HostLevel &L = pb->levels[level];
+    if (count != (long long)L.shifts.size()) {
+        pb->last_error = "sbm_set_shifts: expected " + std::to_string(L.shifts.size()) + " values";
+        return SBM_EINVAL;
+    }
+    for (long long i = 0; i < count; ++i)
+        if (!std::isfinite(shifts[i])) {
+            pb->last_error = "sbm_set_shifts: non-finite shift";
+            return SBM_EINVAL;
+        }
+    std::vector<double> keep(L.shifts);
+    std::copy(shifts, shifts + count, L.shifts.begin());
+    std::string err;
+    int rc = build_blocks(L, pb->opt, err);
+    if (rc) {
+        // leave the problem as it was
+        L.shifts.swap(keep);
+        std::string e2;
+        build_blocks(L, pb->opt, e2);
+        pb->last_error = "sbm_set_shifts: " + err;
+        return rc;
+    }
+    std::vector<double> Ainv;
+    if (level == 0) {
+        coarse_matrix(L, pb->opt.alpha, pb->opt.ext, pb->A0);
+        Ainv = pb->A0;
+        if (!invert(Ainv.data(), pb->coarse.n, 1e-14, 0.0)) {
+            pb->last_error = "sbm_set_shifts: singular coarsest-level matrix";
+            return SBM_ESINGULAR;
+        }
+    }
+    if (!pb->host_only) {
+        HIPCHK(hipSetDevice(pb->opt.device));
+        HIPCHK(hipStreamSynchronize(pb->stream));
+        if ((rc = refresh_level<double>(pb, L, pb->dev64[level])) ||
+            (rc = refresh_level<float>(pb, L, pb->dev32[level])))
+            return rc;
+        if (level == 0)
+            HIPCHK(hipMemcpy(pb->coarse.Ainv64, Ainv.data(), Ainv.size() * sizeof(double), hipMemcpyHostToDevice));
+        if (level > 0) std::vector<double>().swap(L.Dbnd);  // only the coarsest keeps D
+    }
+    return SBM_OK;
+}
+
+int sbm_set_shifts(sbm_problem *pb, int level, const double *shifts, long long count) {
+    try {
+        return set_shifts_body(pb, level, shifts, count);
+    } catch (const std::bad_alloc &) {
+        return SBM_ENOMEM;
+    } catch (...) {
+        return SBM_EINVAL;
+    }
 }
 
 int sbm_cell_block(const sbm_problem *pb, int level, int cell, int inverse, double *out) {

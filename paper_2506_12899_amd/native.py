@@ -63,6 +63,7 @@ SIGNATURES = [
     ("sbm_active_cells", C.c_int, [_VP, C.c_int, C.POINTER(C.c_int), C.c_longlong]),
     ("sbm_level_info", C.c_int, [_VP, C.c_int] + [C.POINTER(C.c_int)] * 5),
     ("sbm_shifts", C.c_int, [_VP, C.c_int, C.POINTER(C.c_double), C.c_longlong]),
+    ("sbm_set_shifts", C.c_int, [_VP, C.c_int, C.POINTER(C.c_double), C.c_longlong]),
     ("sbm_rhs", C.c_int, [_VP, FIELD_FN, FIELD_FN, _VP, _VP]),
     ("sbm_apply", C.c_int, [_VP, _VP, _VP, C.c_int]),
     ("sbm_vcycle", C.c_int, [_VP, _VP, _VP, C.c_int]),

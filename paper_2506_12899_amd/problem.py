@@ -119,6 +119,16 @@ class Problem:
         N.check(N.lib().sbm_shifts(self._h, level, out.ctypes.data_as(C.POINTER(C.c_double)), out.size), self._h)
         return out
 
+    def set_shifts(self, shifts, level=-1):
+        """Load externally supplied shifts (test hook, sbm_set_shifts)."""
+        info = self.level_info(level)
+        nf = (info["p"] + 1) ** (self.dim - 1)
+        a = np.ascontiguousarray(shifts, dtype=np.float64)
+        if a.shape != (info["n_surrogate_faces"], nf, self.dim):
+            raise ValueError(f"shifts of shape {a.shape}, level {level} needs "
+                             f"{(info['n_surrogate_faces'], nf, self.dim)}")
+        N.check(N.lib().sbm_set_shifts(self._h, level, a.ctypes.data_as(C.POINTER(C.c_double)), a.size), self._h)
+
     def cell_block(self, cell, level=-1, inverse=False):
         info = self.level_info(level)
         nc = (info["p"] + 1) ** self.dim

@@ -342,3 +342,36 @@ def test_solve_one_level_exact_preconditioner(fp32):
     assert st["converged"] and st["rel_residual"] <= 1e-8 and st["iterations"] <= 2
     H = mg.Hierarchy(oracle_geometry(geo), 2, 8, 1, coarse_dofs=4096)
     assert np.linalg.norm(b.cpu().numpy() - H.fine.A @ x.cpu().numpy()) <= 1e-8 * np.linalg.norm(b.cpu().numpy())
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_loaded_shifts_isolate_kernel_parity(fp32):
+    """Shifts supplied from outside (sbm_set_shifts; every level's computed
+    shifts perturbed by up to 0.2 h): apply and V-cycle against the oracle
+    built on the same shifts, so that a closest-point difference cannot hide
+    or cause a kernel difference."""
+    from paper_2506_12899_amd.problem import Problem
+    dev = _gpu()
+    geo = workloads.balls([[0.03, -0.02, 0.01]], [0.75])
+    print(f"[parity] loaded shifts fp32={fp32}", flush=True)
+    pb = Problem(geo, 8, 2, device=0, coarse_dofs=0)
+    H = mg.Hierarchy(oracle_geometry(geo), 3, 8, 2, coarse_dofs=0)
+    rng = np.random.default_rng(7)
+    for l, L in enumerate(H.levels):
+        L.shifts = L.shifts + rng.uniform(-0.2, 0.2, L.shifts.shape) * L.h
+        L.assemble()
+        H.inv[l] = mg.cell_inverses(L, L.D, 0.0)
+        pb.set_shifts(L.shifts, l)
+    H.A0inv = np.linalg.inv(H.levels[0].A.toarray())
+    L = H.fine
+    x = workloads.random_vector(L.n_dofs, seed=71)
+    dt = torch.float32 if fp32 else torch.float64
+    y = pb.apply(_t(x, dev, dt)).cpu().numpy().astype(np.float64)
+    assert _rel(y, L.A @ x) <= (TOL32 if fp32 else TOL64)
+    ref = H.vcycle(x)
+    z = pb.vcycle(_t(x, dev, dt)).cpu().numpy().astype(np.float64)
+    if fp32:
+        print(f"[parity] loaded shifts FP32 cycle: {_rel(z, ref):.2e}", flush=True)
+        assert _rel(z, ref) <= 4e-5        # as the unperturbed 8^3 Q2 sphere (FP32_CYCLE_BAR)
+    else:
+        _check64(z, ref, "loaded shifts")

@@ -166,3 +166,34 @@ def test_stabilised_form_matches_oracle(name, geo, n, p, kw):
             assert np.abs(B - H.inv[l][K]).max() <= 1e-10 * np.abs(H.inv[l][K]).max(), (l, K)
     if kw.get("stab", 0) > 0 and name != "star":
         assert floored > 0      # the floor is exercised
+
+
+@pytest.mark.parametrize("level", [-1, 0])
+def test_set_shifts_rebuilds_blocks_like_oracle(level):
+    """Test hook sbm_set_shifts: externally supplied shifts (the computed ones
+    perturbed by up to 0.2 h) give the blocks and inverses the oracle builds
+    from the same shifts; a wrong count is refused and leaves the problem as
+    it was."""
+    from paper_2506_12899_amd import native as Nn
+    geo = workloads.balls([[0.03, -0.02, 0.01]], [0.75])
+    pb = _problem(geo, 8, 2, coarse_dofs=0)
+    H = mg.Hierarchy(oracle_geometry(geo), 3, 8, 2, coarse_dofs=0)
+    lv = len(H.levels) - 1 if level == -1 else level
+    L0 = H.levels[lv]
+    sh = L0.shifts + np.random.default_rng(3).uniform(-0.2, 0.2, L0.shifts.shape) * L0.h
+    pb.set_shifts(sh, level)
+    assert np.array_equal(pb.shifts(level), sh)
+    L = dg.Level(oracle_geometry(geo), 3, L0.n, L0.p, shifts=sh)
+    inv = mg.cell_inverses(L, L.D, 0.0)
+    for K in L.boundary_cells:
+        D = pb.cell_block(int(K), lv)
+        assert np.abs(D - L.D[K]).max() <= 1e-12 * np.abs(L.D[K]).max()
+        B = pb.cell_block(int(K), lv, inverse=True)
+        assert np.abs(B - inv[K]).max() <= 1e-10 * np.abs(inv[K]).max()
+    if lv == 0:
+        A0 = pb.coarse_matrix()
+        assert np.abs(A0 - L.A.toarray()).max() <= 1e-12 * np.abs(A0).max()
+    with pytest.raises(Nn.SbmError):
+        Nn.check(Nn.lib().sbm_set_shifts(pb._h, level, sh.ctypes.data_as(C.POINTER(C.c_double)), sh.size - 1),
+                 pb._h)
+    assert np.array_equal(pb.shifts(level), sh)
