@@ -1,0 +1,193 @@
+"""Paper-faithful configurations (the setting of the paper's Sec. 5).
+
+    python -m paper_2506_12899_amd.paper_mode iterations --dim 2 --p 1 --levels 1-6 [--lambdas 1,0.75,0.5,0.25]
+    python -m paper_2506_12899_amd.paper_mode shifts --dim 2 --p 2 --levels 1-7
+
+The paper's numerical study (Sec. 5 opening, Sec. 5.2-5.4):
+  * background box [-1.01, 1.01]^d; refinement level k has 4 * 2^k cells per
+    direction (the coarsest multigrid mesh is the initial 4^d one);
+  * active cells by the volume-fraction rule, fraction > lambda (Sec. 2.1),
+    lambda in {1, 0.75, 0.5, 0.25};
+  * the unit disk / sphere with u = 2 cos(x_1) sin(x_2), f = -Lap u = 2 u,
+    g = u on Gamma (Sec. 5.1); the deformed 2D domain
+    phi = (1 - 3/4 sin^2(pi x)) (x^2 + y^2) - 1/5 with u = phi + 1 (Sec. 5.4);
+  * GMRES to a 1e-12 relative residual, failure beyond 100 iterations;
+    omega = 1 (p <= 2), 0.8 (p = 3, Sec. 5.3).
+Kept from this library's readings: penalties c (p+1)^2 / h (the paper's
+unscaled "sigma_Gamma = 5, sigma_F = 1" read with the O(p^2/h) scaling it
+states), red-black cell order, the restarted FGMRES(30).
+"""
+import argparse
+import json
+import math
+import sys
+
+import numpy as np
+
+from . import workloads
+
+BOX = (-1.01, 1.01)
+LAMBDAS = (1.0, 0.75, 0.5, 0.25)
+
+
+def _unit_solution():
+    def u(X):
+        X = np.atleast_2d(X)
+        return 2.0 * np.cos(X[:, 0]) * np.sin(X[:, 1])
+
+    def f(X):
+        return 2.0 * u(X)
+    return workloads.Solution("2 cos(x1) sin(x2)", u, f)
+
+
+def _deformed_phi(X):
+    X = np.atleast_2d(X)
+    x, y = X[:, 0], X[:, 1]
+    return (1.0 - 0.75 * np.sin(math.pi * x) ** 2) * (x * x + y * y) - 0.2
+
+
+def deformed_geometry():
+    """The deformed 2D domain of Sec. 5.4 as a general level set (callback
+    kind: phi, gradient and Hessian; closest points by the Lagrangian Newton
+    iteration of Sec. 4.2)."""
+    def grad(X):
+        X = np.atleast_2d(X)
+        x, y = X[:, 0], X[:, 1]
+        a = 1.0 - 0.75 * np.sin(math.pi * x) ** 2
+        da = -1.5 * math.pi * np.sin(math.pi * x) * np.cos(math.pi * x)
+        r2 = x * x + y * y
+        return np.stack([da * r2 + 2 * a * x, 2 * a * y], axis=1)
+
+    def hess(X):
+        X = np.atleast_2d(X)
+        x, y = X[:, 0], X[:, 1]
+        a = 1.0 - 0.75 * np.sin(math.pi * x) ** 2
+        da = -0.75 * math.pi * np.sin(2 * math.pi * x)
+        dda = -1.5 * math.pi ** 2 * np.cos(2 * math.pi * x)
+        r2 = x * x + y * y
+        H = np.zeros((len(x), 2, 2))
+        H[:, 0, 0] = dda * r2 + 4 * da * x + 2 * a
+        H[:, 0, 1] = H[:, 1, 0] = 2 * da * y
+        H[:, 1, 1] = 2 * a
+        return H
+    return workloads.LevelSet(2, _deformed_phi, grad, hess)
+
+
+def _deformed_solution():
+    def u(X):
+        return _deformed_phi(X) + 1.0
+
+    def f(X):
+        X = np.atleast_2d(X)
+        x, y = X[:, 0], X[:, 1]
+        a = 1.0 - 0.75 * np.sin(math.pi * x) ** 2
+        da = -0.75 * math.pi * np.sin(2 * math.pi * x)
+        dda = -1.5 * math.pi ** 2 * np.cos(2 * math.pi * x)
+        r2 = x * x + y * y
+        return -(dda * r2 + 4 * da * x + 4 * a)
+    return workloads.Solution("phi + 1", u, f)
+
+
+def problem(kind, dim, level, p, lam):
+    """A workloads.Problem in the paper's setting.  kind: "ball" (unit disk or
+    sphere) or "deformed" (2D, Sec. 5.4)."""
+    n = 4 * 2 ** level
+    opts = {"lo": BOX[0], "hi": BOX[1], "lambda_frac": float(lam), "coarse_dofs": 0, "coarse_min": 4}
+    if kind == "ball":
+        geo, sol = workloads.balls([[0.0] * dim], [1.0]), _unit_solution()
+    elif kind == "deformed":
+        if dim != 2:
+            raise ValueError("the deformed domain is 2D")
+        geo, sol = deformed_geometry(), _deformed_solution()
+    else:
+        raise ValueError(kind)
+    return workloads.Problem(f"paper_{kind}{dim}d_l{level}_q{p}_lam{lam}", geo, n, p, sol, opts)
+
+
+def signed_shift_extremes(pb):
+    """min and max over the finest level's surrogate quadrature points of the
+    shift length |d| / h, signed by d . n~ (negative where d points into the
+    surrogate domain), as in Fig. 3."""
+    sh = pb.shifts()
+    info = pb.level_info()
+    cells = pb.active_cells()
+    d = pb.dim
+    h = (BOX[1] - BOX[0]) / pb.n
+    act = {tuple(c) for c in cells.tolist()}
+    nrm = []
+    for c in cells.tolist():
+        for k in range(d):
+            for s in (0, 1):
+                m = list(c)
+                m[k] += 2 * s - 1
+                if not (0 <= m[k] < pb.n) or tuple(m) not in act:
+                    v = np.zeros(d)
+                    v[k] = 2 * s - 1
+                    nrm.append(v)
+    nrm = np.array(nrm)
+    assert len(nrm) == info["n_surrogate_faces"]
+    dn = np.einsum('fqc,fc->fq', sh, nrm)
+    val = np.sign(dn) * np.linalg.norm(sh, axis=2) / h
+    return float(val.min()), float(val.max())
+
+
+def iterations(kind, dim, p, levels, lambdas=LAMBDAS, tol=1e-12, max_iter=100, nu=1, log=None):
+    """GMRES iterations to tol for each (lambda, level); 100 + 1 marks failure
+    (not converged within max_iter)."""
+    import torch
+    from .problem import Problem
+    out = []
+    for lam in lambdas:
+        for lv in levels:
+            pr = problem(kind, dim, lv, p, lam)
+            try:
+                pb = Problem(pr.geometry, pr.n, pr.p, device=0, nu_pre=nu, nu_post=nu, **pr.opts)
+            except Exception as e:  # a level without active cells, a singular block: recorded
+                out.append(dict(lam=lam, level=lv, error=str(e)))
+                continue
+            b = pb.rhs(pr.solution.f, pr.solution.u)
+            _, st = pb.solve(b, tol=tol, max_iter=max_iter)
+            torch.cuda.synchronize()
+            rec = dict(lam=lam, level=lv, n=pr.n, dofs=int(pb.n_dofs), iterations=st["iterations"],
+                       converged=st["converged"], rel=st["rel_residual"])
+            if log:
+                log(rec)
+            out.append(rec)
+            del pb
+    return out
+
+
+def _levels(s):
+    a, _, b = s.partition("-")
+    return list(range(int(a), int(b or a) + 1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["iterations", "shifts"])
+    ap.add_argument("--kind", default="ball")
+    ap.add_argument("--dim", type=int, default=2)
+    ap.add_argument("--p", type=int, default=1)
+    ap.add_argument("--levels", default="1-5")
+    ap.add_argument("--lambdas", default="1,0.75,0.5,0.25")
+    ap.add_argument("--nu", type=int, default=1, help="smoothing steps before and after the coarse correction")
+    args = ap.parse_args()
+    lams = [float(v) for v in args.lambdas.split(",")]
+    if args.what == "shifts":
+        from .problem import Problem
+        rows = []
+        for lam in lams:
+            for lv in _levels(args.levels):
+                pr = problem(args.kind, args.dim, lv, args.p, lam)
+                pb = Problem(pr.geometry, pr.n, pr.p, device=-1, **pr.opts)
+                lo, hi = signed_shift_extremes(pb)
+                rows.append(dict(lam=lam, level=lv, min=lo, max=hi))
+        print(json.dumps(rows))
+        return
+    rows = iterations(args.kind, args.dim, args.p, _levels(args.levels), lams, nu=args.nu,
+                      log=lambda r: print(json.dumps(r), file=sys.stderr, flush=True))
+    print(json.dumps(rows))
+
+
+if __name__ == "__main__":
+    main()

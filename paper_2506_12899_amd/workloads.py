@@ -47,6 +47,21 @@ class Geometry:
         return np.linalg.norm(X, axis=1) - (self.star_r0 + self.star_a * np.sin(self.star_k * th))
 
 
+class LevelSet:
+    """A general level set Omega = {phi < 0} given by vectorised callables
+    phi(X) -> (m,), grad(X) -> (m, dim), hess(X) -> (m, dim, dim) on rows of X
+    (the library's callback kind)."""
+
+    kind = "callback"
+
+    def __init__(self, dim, phi, grad, hess):
+        self.dim = dim
+        self._phi, self.grad, self.hess = phi, grad, hess
+
+    def phi(self, X):
+        return self._phi(np.atleast_2d(X))
+
+
 def balls(centers, radii):
     c = np.atleast_2d(np.asarray(centers, dtype=np.float64))
     return Geometry("balls", c.shape[1], c, np.atleast_1d(np.asarray(radii, dtype=np.float64)))

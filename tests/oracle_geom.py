@@ -21,4 +21,6 @@ def oracle_geometry(g):
         def hess(X):
             return np.broadcast_to(2.0 * Ainv2, (X.shape[0], 3, 3))
         return geometry.LevelSet(phi, grad, hess, 3)
+    if g.kind == "callback":
+        return geometry.LevelSet(g.phi, g.grad, g.hess, g.dim)
     return geometry.Star2D(g.star_r0, g.star_a, g.star_k)

@@ -197,3 +197,22 @@ def test_set_shifts_rebuilds_blocks_like_oracle(level):
         Nn.check(Nn.lib().sbm_set_shifts(pb._h, level, sh.ctypes.data_as(C.POINTER(C.c_double)), sh.size - 1),
                  pb._h)
     assert np.array_equal(pb.shifts(level), sh)
+
+
+def test_paper_setting_shift_extremes_match_fig3():
+    """The library in the paper's setting (paper_mode.problem: box
+    [-1.01, 1.01]^2, 4 * 2^k cells, volume-fraction rule) reproduces the
+    printed Fig. 3 extremes at levels 1-5 (see the oracle pin of the same
+    figure)."""
+    from paper_2506_12899_amd import paper_mode
+    from paper_2506_12899_amd.problem import Problem
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "fig3_shift_extremes.txt"))
+    for lam, lv, plo, phi_ in rows:
+        if lv > 5:
+            continue
+        pr = paper_mode.problem("ball", 2, int(lv), 3, lam)
+        pb = Problem(pr.geometry, pr.n, pr.p, device=-1, **pr.opts)
+        lo, hi = paper_mode.signed_shift_extremes(pb)
+        assert abs(hi - phi_) <= 6e-5, (lam, lv, hi, phi_)
+        if lam < 1.0:
+            assert abs(lo - plo) <= 6e-5, (lam, lv, lo, plo)
