@@ -111,6 +111,16 @@ typedef struct {
                              of the level's interior block, are raised to that floor in its
                              inverse, B_K = sum_i v_i u_i^T / max(sigma_i, stab s_int); the
                              operator itself is unchanged                                   */
+    int smoother;         /* 0 (default): multiplicative cell-wise smoother, red-black SSOR
+                             (colours 0, 1, 1, 0 per step); 1: the additive cell-wise
+                             smoother (block Jacobi, Sec. 3.1) accelerated by Chebyshev
+                             polynomials (Sec. 5.3): one smoothing step is cheb_degree
+                             block-Jacobi updates with the Chebyshev weights for the interval
+                             [l/cheb_range, l], l = 1.2 x the largest eigenvalue modulus of
+                             B A found by 25 power iterations from the all-ones vector at
+                             setup (per level); no learned correction; transfers unfused  */
+    int cheb_degree;      /* block-Jacobi updates per Chebyshev smoothing step (default 3)   */
+    double cheb_range;    /* ratio of the interval's ends (default 20)                       */
     int device;           /* HIP device ordinal (default 0); < 0 = host-only setup for tests:
                              no device data, the device entry points return SBM_EINVAL     */
     void *stream;         /* hipStream_t for all work (default NULL = null stream)            */

@@ -22,7 +22,12 @@ Readings (listed in the design notes):
     cell is dropped, prolongation from an inactive parent gives zero;
   * coarse solver: a direct solve with the dense matrix of the coarsest level;
   * min_neighbours (the k-core rule of the active set) shapes the finest mesh
-    only; the h-coarsened levels keep the plain active-cell rule.
+    only; the h-coarsened levels keep the plain active-cell rule;
+  * smoother = 1: the additive variant of Sec. 3.1 (block Jacobi) inside a
+    Chebyshev iteration (Sec. 5.3 mentions both): the interval of B A is
+    [lmax / cheb_range, lmax], lmax = 1.2 x the dominant eigenvalue modulus
+    from 25 power iterations started at the all-ones vector (range 20, degree
+    3 by default: the values the interval is taken with are a reading).
 """
 import numpy as np
 import scipy.sparse as sp
@@ -67,7 +72,7 @@ class Hierarchy:
     active DoFs; the last level is solved exactly."""
 
     def __init__(self, geom, d, n, p, coarse_min=3, coarse_dofs=2048, omega=None, nu_pre=1, nu_post=1,
-                 stab=0.0, **kw):
+                 stab=0.0, smoother=0, cheb_degree=3, cheb_range=20.0, **kw):
         fine_first = [dg.Level(geom, d, n, q, **kw) for q in range(p, 0, -1)]
         ckw = {k: v for k, v in kw.items() if k != "min_neighbours"}   # finest mesh only
         nn = n
@@ -85,6 +90,9 @@ class Hierarchy:
         A0 = self.levels[0].A.toarray()
         self.A0inv = np.linalg.inv(A0) if A0.size else A0
         self.learned = None   # optional (omega_K, U_K, V_K) on the finest level
+        self.smoother, self.cheb_degree, self.cheb_range = int(smoother), int(cheb_degree), float(cheb_range)
+        self.cheb_lmax = [None] + [self._largest_eigenvalue(l) for l in range(1, len(self.levels))] \
+            if self.smoother == 1 else None
 
     @staticmethod
     def _block_inverses(L, stab=0.0):
@@ -146,6 +154,48 @@ class Hierarchy:
             z = self.colour_update(l, z, b, c)
         return z
 
+    # ------------------------------------------ additive smoother + Chebyshev
+    def block_jacobi(self, l, r):
+        """B r: every cell's inverse on its residual at once (Sec. 3.1,
+        additive subspace correction without the weight)."""
+        L = self.levels[l]
+        return np.einsum('kij,kj->ki', self.inv[l], r.reshape(L.n_act, L.N)).ravel()
+
+    def _largest_eigenvalue(self, l):
+        """1.2 x the modulus of the dominant eigenvalue of B A, by 25 power
+        iterations from the normalised all-ones vector."""
+        L = self.levels[l]
+        v = np.full(L.n_dofs, 1.0 / np.sqrt(L.n_dofs))
+        lam = 0.0
+        for _ in range(25):
+            t = self.block_jacobi(l, L.A @ v)
+            lam = np.linalg.norm(t)
+            v = t / lam
+        return 1.2 * lam
+
+    def chebyshev_step(self, l, z, b):
+        """cheb_degree additive block-Jacobi updates with Chebyshev weights
+        for the interval [lmax / range, lmax] of B A (Sec. 5.3: the additive
+        smoother wrapped in a Chebyshev iteration): the Chebyshev iteration for
+        A x = b preconditioned by B, started from z."""
+        lmax = self.cheb_lmax[l]
+        lmin = lmax / self.cheb_range
+        theta, delta = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+        sigma = theta / delta
+        L = self.levels[l]
+        d = self.block_jacobi(l, b - L.A @ z) / theta
+        z = z + d
+        rho_old = 1.0 / sigma
+        for _ in range(1, self.cheb_degree):
+            rho = 1.0 / (2.0 * sigma - rho_old)
+            d = rho * rho_old * d + 2.0 * rho / delta * self.block_jacobi(l, b - L.A @ z)
+            z = z + d
+            rho_old = rho
+        return z
+
+    def smoothing_step(self, l, z, b):
+        return self.chebyshev_step(l, z, b) if self.smoother == 1 else self.ssor_step(l, z, b)
+
     # ------------------------------------------------------------ V-cycle
     def vcycle(self, b, l=None):
         if l is None:
@@ -155,12 +205,12 @@ class Hierarchy:
         L = self.levels[l]
         z = np.zeros_like(b)
         for _ in range(self.nu_pre):
-            z = self.ssor_step(l, z, b)
+            z = self.smoothing_step(l, z, b)
         r = b - L.A @ z
         zc = self.vcycle(self.P[l].T @ r, l - 1)
         z = z + self.P[l] @ zc
         for _ in range(self.nu_post):
-            z = self.ssor_step(l, z, b)
+            z = self.smoothing_step(l, z, b)
         return z
 
     @property

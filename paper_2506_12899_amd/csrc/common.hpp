@@ -126,6 +126,10 @@ struct DevLevel {
     T *lw = nullptr, *lU = nullptr, *lV = nullptr;  // n_bnd, n_bnd*nc*4, n_bnd*nc*4
     // level work vectors (coarser levels and the FP32 cycle)
     T *z = nullptr, *b = nullptr, *r = nullptr;
+    // Chebyshev-accelerated block-Jacobi smoother: search direction and the
+    // estimate of the largest eigenvalue of B A on this level
+    T *dcheb = nullptr;
+    double cheb_lmax = 0.0;
 };
 
 struct CoarseDev {

@@ -99,6 +99,12 @@ int launch_coarse_solve_prolong(int d, int n, const double *A, const TX *x, TX *
                                 hipStream_t st);
 template <typename T>
 int launch_fill(long long n, T *x, T v, hipStream_t st);
+// Additive (block-Jacobi) update of every active cell of a level:
+// d_K = alpha d_K + beta B_K r_K (alpha = 0: d is not read), then z_K += d_K
+// when z is given.  B_K: the cell's (transposed) inverse.
+template <typename T>
+int launch_block_jacobi(int n_act, int nc, const int *bnd_of, const T *Bint_t, const T *Bbnd_t, const T *r, T *d,
+                        T *z, T alpha, T beta, hipStream_t st);
 int launch_cast_d2f(long long n, const double *x, float *y, hipStream_t st);
 int launch_cast_f2d(long long n, const float *x, double *y, hipStream_t st);
 // Gram-Schmidt kernels.  Partial-sum buffers hold gs_partials_max() doubles;

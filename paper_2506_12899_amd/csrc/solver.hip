@@ -290,8 +290,8 @@ int resid_restrict(sbm_problem *pb, int l, const T *z, const T *b, T *bc, T *zc 
     // colour-0 residual is zero up to rounding: a p-transfer then computes only
     // colour 1 (the cells map one to one, so the colour-0 part of bc is zero).
     const bool learned_here = pb->learned_on && l == (int)pb->levels.size() - 1 && Df.lw != nullptr;
-    const bool c1_only = nch == 1 && pb->opt.nu_pre > 0 && pb->opt.omega == 1.0 && pb->opt.allow_singular == 0 &&
-                         pb->levels[l].n_clipped == 0 && !learned_here;
+    const bool c1_only = nch == 1 && pb->opt.smoother == 0 && pb->opt.nu_pre > 0 && pb->opt.omega == 1.0 &&
+                         pb->opt.allow_singular == 0 && pb->levels[l].n_clipped == 0 && !learned_here;
     KCHK(launch_resid_restrict<T>(Df.d, Df.p, Dc.n_act, nch, Dc.p + 1, nch == 1 ? nullptr : Df.rr_perm,
                                   nch == 1 ? nullptr : Df.rr_grp, z, b, bc, ca, Df.kref, tr, pb->stream,
                                   zc != nullptr ? &zs : nullptr, c1_only));
@@ -355,11 +355,77 @@ int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false, 
 // restriction forms the coarser level's zero-start update and the coarser
 // level's last smoothing kernels add its final z into this level's z, so
 // neither needs a launch of its own.
+// One Chebyshev smoothing step on level l: cheb_degree additive block-Jacobi
+// updates z += d_k, d_k = a_k d_(k-1) + c_k B (b - A z), with the weights of
+// the Chebyshev iteration for the eigenvalue interval [lmax / range, lmax] of
+// B A (theta, delta: its centre and half width; rho_k = 1 / (2 sigma -
+// rho_(k-1)), sigma = theta / delta, a_k = rho_k rho_(k-1), c_k = 2 rho_k /
+// delta, d_0 = B r / theta).  from_zero: z = 0 on entry (the first residual
+// is b).
+template <typename T>
+int cheb_smooth(sbm_problem *pb, int l, const T *b, T *z, bool from_zero) {
+    auto &D = devlevels<T>(pb)[l];
+    const double lmax = D.cheb_lmax, lmin = lmax / pb->opt.cheb_range;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+    double rho_old = 1.0 / sigma;
+    for (int k = 0; k < pb->opt.cheb_degree; ++k) {
+        const T *r = b;
+        if (!(k == 0 && from_zero)) {
+            KCHK(launch_cellop<T>(D.d, D.p, OP_RESID, 0, D.n_act, z, D.r, b,
+                                  [&] {
+                                      CellArgs<T> a = cell_args(D, false);
+                                      a.batch_start = D.batch_start;
+                                      a.nbatch = D.nbatch;
+                                      return a;
+                                  }(),
+                                  D.kref, pb->stream));
+            r = D.r;
+        }
+        double alpha = 0.0, beta = 1.0 / theta;
+        if (k > 0) {
+            const double rho = 1.0 / (2.0 * sigma - rho_old);
+            alpha = rho * rho_old;
+            beta = 2.0 * rho / delta;
+            rho_old = rho;
+        }
+        KCHK(launch_block_jacobi<T>(D.n_act, D.nc, D.bnd_of, D.Bint_t, D.Bbnd_t, r, D.dcheb, z, (T)alpha, (T)beta,
+                                    pb->stream));
+    }
+    return SBM_OK;
+}
+
 template <typename T>
 int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z, const double *b64 = nullptr, bool started = false,
-               const EmitArgs<T> *em = nullptr, bool *emitted = nullptr) {
+               const EmitArgs<T> *em = nullptr, bool *emitted = nullptr);
+
+// V-cycle with the Chebyshev block-Jacobi smoother (separate transfer kernels)
+template <typename T>
+int vcycle_cheb(sbm_problem *pb, int l, const T *b, T *z, const double *b64) {
+    auto &D = devlevels<T>(pb)[l];
+    const long long nd = (long long)D.n_act * D.nc;
+    if constexpr (std::is_same<T, float>::value) {
+        if (b64 != nullptr) KCHK(launch_cast_d2f(nd, b64, const_cast<float *>(b), pb->stream));
+    }
+    int rc;
+    KCHK(launch_fill<T>(nd, z, T(0), pb->stream));
+    for (int s = 0; s < pb->opt.nu_pre; ++s)
+        if ((rc = cheb_smooth<T>(pb, l, b, z, s == 0))) return rc;
+    auto &Dc = devlevels<T>(pb)[l - 1];
+    if ((rc = resid_restrict<T>(pb, l, z, b, Dc.b, nullptr))) return rc;
+    if ((rc = l - 1 == 0 ? vcycle_rec<T>(pb, 0, Dc.b, Dc.z) : vcycle_cheb<T>(pb, l - 1, Dc.b, Dc.z, nullptr)))
+        return rc;
+    if ((rc = prolong_add<T>(pb, l, Dc.z, z))) return rc;
+    for (int s = 0; s < pb->opt.nu_post; ++s)
+        if ((rc = cheb_smooth<T>(pb, l, b, z, false))) return rc;
+    return SBM_OK;
+}
+
+template <typename T>
+int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z, const double *b64, bool started, const EmitArgs<T> *em,
+               bool *emitted) {
     auto &D = devlevels<T>(pb)[l];
     if (emitted) *emitted = false;
+    if (l > 0 && pb->opt.smoother == 1) return vcycle_cheb<T>(pb, l, b, z, b64);
     if (l == 0) {
         if constexpr (std::is_same<T, float>::value) {
             // a one-level hierarchy: the FP32 copy of the right-hand side first
@@ -482,6 +548,9 @@ int sbm_default_options(int dim, int p, sbm_options *o) {
     o->lambda_frac = 0.0;
     o->frac_m = 16;
     o->min_neighbours = 0;
+    o->smoother = 0;
+    o->cheb_degree = 3;
+    o->cheb_range = 20.0;
     o->stab = 0.0;
     o->device = 0;
     o->stream = nullptr;
@@ -494,6 +563,41 @@ int sbm_destroy(sbm_problem *pb) {
     for (void *q : pb->allocations) hipFree(q);
     if (pb->pinned) hipHostFree(pb->pinned);
     delete pb;
+    return SBM_OK;
+}
+
+// Chebyshev smoother: direction vectors of every smoothed level and the
+// largest eigenvalue modulus of B A per level, by 25 power iterations in FP64
+// from the normalised all-ones vector (v <- B A v / |B A v|; the estimate is
+// the last |B A v|), taken 1.2 times as the interval's upper end.
+static int chebyshev_setup(sbm_problem *pb) {
+    int rc;
+    double *part = nullptr, *scal = nullptr;
+    if ((rc = dalloc(pb, &part, (size_t)sbm::gs_partials_max())) || (rc = dalloc(pb, &scal, (size_t)2))) return rc;
+    hipStream_t s = pb->stream;
+    for (size_t l = 1; l < pb->levels.size(); ++l) {
+        auto &D64 = pb->dev64[l];
+        auto &D32 = pb->dev32[l];
+        const long long nd = (long long)D64.n_act * D64.nc;
+        if ((rc = dalloc(pb, &D64.dcheb, (size_t)nd)) || (rc = dalloc(pb, &D32.dcheb, (size_t)nd))) return rc;
+        KCHK(launch_fill<double>(nd, D64.b, 1.0 / std::sqrt((double)nd), s));
+        for (int it = 0; it < 25; ++it) {
+            if ((rc = level_apply<double>(pb, (int)l, OP_APPLY, D64.b, D64.r, nullptr))) return rc;
+            KCHK(launch_block_jacobi<double>(D64.n_act, D64.nc, D64.bnd_of, D64.Bint_t, D64.Bbnd_t, D64.r, D64.dcheb,
+                                             nullptr, 0.0, 1.0, s));
+            KCHK(launch_gs_dots(nd, 0, nullptr, D64.dcheb, part, s));
+            KCHK(launch_gs_reduce(nd, 1, part, scal, s));
+            KCHK(launch_scale(nd, scal, D64.dcheb, D64.b, s));
+        }
+        double lam2 = 0.0;
+        HIPCHK(hipMemcpyAsync(&lam2, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (!(lam2 > 0.0) || !std::isfinite(lam2)) {
+            pb->last_error = "Chebyshev smoother: eigenvalue estimate failed on level " + std::to_string(l);
+            return SBM_ENONFINITE;
+        }
+        D64.cheb_lmax = D32.cheb_lmax = 1.2 * std::sqrt(lam2);
+    }
     return SBM_OK;
 }
 
@@ -513,7 +617,8 @@ static int setup_body(const sbm_geometry *g, int n, int p, const sbm_options *o,
     if (!(op.hi > op.lo) || op.nu_pre < 0 || op.nu_post < 0 || op.coarse_min < 1 || op.coarse_dofs < 0 ||
         (op.ext != 0 && op.ext != 1) || op.penalty_p < 0 || op.penalty_p > 3 || !(op.lambda_frac >= 0.0) ||
         op.lambda_frac > 1.0 || op.frac_m < 1 || op.frac_m > 64 || !(op.stab >= 0.0) || op.min_neighbours < 0 ||
-        op.min_neighbours > 2 * g->dim) {
+        op.min_neighbours > 2 * g->dim || (op.smoother != 0 && op.smoother != 1) || op.cheb_degree < 1 ||
+        op.cheb_degree > 64 || !(op.cheb_range > 1.0)) {
         delete pb;
         return SBM_EINVAL;
     }
@@ -630,6 +735,10 @@ static int setup_body(const sbm_geometry *g, int n, int p, const sbm_options *o,
         if (l > 0) {
             std::vector<double>().swap(pb->levels[l].Dbnd);  // only the coarsest keeps D
         }
+    }
+    if (op.smoother == 1 && (rc = chebyshev_setup(pb))) {
+        *out = pb;
+        return rc;
     }
     const HostLevel &Lf = pb->levels.back();
     size_t nd = (size_t)Lf.n_act * Lf.nc;

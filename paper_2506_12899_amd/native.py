@@ -37,6 +37,7 @@ class Options(C.Structure):
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("coarse_min", C.c_int), ("coarse_dofs", C.c_int),
                 ("vcycle_fp32", C.c_int), ("allow_singular", C.c_int), ("fuse_transfers", C.c_int),
                 ("penalty_p", C.c_int), ("lambda_frac", C.c_double), ("frac_m", C.c_int), ("min_neighbours", C.c_int), ("stab", C.c_double),
+                ("smoother", C.c_int), ("cheb_degree", C.c_int), ("cheb_range", C.c_double),
                 ("device", C.c_int),
                 ("stream", C.c_void_p)]
 

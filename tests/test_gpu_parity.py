@@ -64,6 +64,7 @@ FP32_CYCLE_BAR = {
     "disk_q2_ext0": 1.2e-4, "sphere_q2": 4e-5, "sphere_q2_ext0": 2.5e-5, "sphere_q3": 4e-5,
     "union3_q3": 1e-3, "disk_q2_omega": 3.5e-5, "sphere_q2_nu21": 6.5e-5, "disk_q2_deep": 8e-5,
     "sphere_q2_deep": 6.5e-4, "sphere_q2_penalty_free": 1.2e-4, "disk_q2_penalty_free": 1e-4,
+    "sphere_q2_cheb": 4e-5,
 }
 
 
@@ -99,6 +100,10 @@ CASES = [
     # penalty-free variant (Sec. 2.1 remark, Fig. 1 dashed curves): alpha = -1, sigma_Gamma = 0
     ("disk_q2_penalty_free", workloads.balls([[0.03, -0.02]], [0.7]), 24, 2, {"alpha": -1.0, "c_G": 0.0}),
     ("sphere_q2_penalty_free", workloads.balls([[0.03, -0.02, 0.01]], [0.75]), 8, 2, {"alpha": -1.0, "c_G": 0.0}),
+    # the additive cell-wise smoother inside a Chebyshev iteration (Sec. 3.1, Sec. 5.3)
+    ("disk_q2_cheb", workloads.balls([[0.03, -0.02]], [0.7]), 24, 2, {"smoother": 1}),
+    ("sphere_q2_cheb", workloads.balls([[0.03, -0.02, 0.01]], [0.75]), 8, 2, {"smoother": 1, "cheb_degree": 4}),
+    ("sphere_q3_stab_cheb", workloads.balls([[0.03, -0.02, 0.01]], [0.8]), 12, 3, dict(STAB3, smoother=1)),
     # a coarsest level of one to three cells (fewer coarse DoFs than lanes of
     # the coarse-solve kernel's row loop)
     ("small_disk_q2_deep", workloads.balls([[0.25, 0.25]], [0.3]), 16, 2, {"coarse_dofs": 0}),
@@ -282,6 +287,9 @@ SOLVE3_CASES = [
     ("sphere_q3_stab_fp32", workloads.balls([[0.0, 0.0, 0.0]], [0.8]), 16, 3, dict(STAB3, vcycle_fp32=1)),
     ("two_balls_q3_stab", workloads.balls([[-0.3, 0.05, 0.0], [0.35, -0.05, 0.02]], [0.55, 0.45]), 16, 3, STAB3),
     ("union3_q3_stab", workloads.eight_balls(0), 16, 3, STAB3),
+    ("sphere_q3_stab_cheb", workloads.balls([[0.0, 0.0, 0.0]], [0.8]), 16, 3, dict(STAB3, smoother=1)),
+    ("sphere_q3_stab_cheb_fp32", workloads.balls([[0.0, 0.0, 0.0]], [0.8]), 16, 3,
+     dict(STAB3, smoother=1, vcycle_fp32=1)),
 ]
 
 
