@@ -233,6 +233,39 @@ def cpu_baseline(prob, gpu_its, budget_s=30.0, max_dofs=2_000_000):
     return dict(base, value=t, sample=sample)
 
 
+def learned_leg(pb, prob, b, x, torch, args, t32, st32):
+    """The learned boundary-cell correction: trained (outside the timed region)
+    on 40 seeded sphere/ellipsoid geometries at 16^3 from the method's own
+    iterations, installed on this problem (BF16 inference), then the FP32 +
+    learned solve timed like the others; the judge keeps it only if it needs
+    fewer iterations than the FP32 solve without it."""
+    from paper_2506_12899_amd import learned
+    from paper_2506_12899_amd.problem import Problem
+    t0 = time.perf_counter()
+    data = learned.generate(lambda g, n, p: Problem(g, n, p, device=0, **prob.opts), range(1, 41), 16, 3, (0, 3), 2,
+                            device=torch.device("cuda", 0), log=lambda m: None)
+    net = learned.MLP(data[0].shape[1], data[1].shape[1], 64, device=torch.device("cuda", 0), omega=0.8)
+    hist = learned.train(net, data, epochs=20, batch=4096, lr=1e-3, log=lambda m: None, time_budget=30.0)
+    train_s = time.perf_counter() - t0
+    learned.install(pb, net)
+    pb.set_vcycle_fp32(1)
+    _, st = pb.solve(b, x, tol=1e-8, max_iter=args.max_iter)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = pb.solve(b, x, tol=1e-8, max_iter=args.max_iter)
+    torch.cuda.synchronize()
+    tl = (time.perf_counter() - t0) / args.steps
+    better = st["converged"] and (not st32["converged"] or st["iterations"] < st32["iterations"])
+    learned.use(pb, False)
+    print(f"[bench] FP32 + learned: {tl * 1e3:.2f} ms, {st['iterations']} its, rel {st['rel_residual']:.2e}; "
+          f"judge keeps {'learned' if better else 'plain'}", file=sys.stderr, flush=True)
+    return {"fp32_learned_s": tl, "iterations": st["iterations"], "converged": bool(st["converged"]),
+            "rel_residual": st["rel_residual"], "judge_keeps": "learned" if better else "plain",
+            "kept_s": tl if better else t32, "train_s": train_s, "train_samples": int(data[0].shape[0]),
+            "loss_first": hist[0], "loss_last": hist[-1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +275,8 @@ def main():
     ap.add_argument("--extra", default="star512_q2",
                     help="comma-separated workloads whose solve times are added as extra keys ('' for none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-correction leg (3D Q3 workloads: train, then FP32 + learned solve)")
     ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--max-iter", type=int, default=300, help="FGMRES iteration cap (failure beyond it)")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -362,6 +397,8 @@ def main():
     out["smoother_block_gflops"] = blk_flops / ts32 / 1e9
     out["smoother_block_util_vs_fp32_valu"] = blk_flops / ts32 / 78.6e12
     out["smoother_block_util_vs_fp32_mfma"] = blk_flops / ts32 / 157.3e12
+    if not args.no_learned and prob.dim == 3 and prob.p == 3:
+        out["learned"] = learned_leg(pb, prob, b, x, torch, args, t32, st32)
     extra = {}
     for name in [w for w in args.extra.split(",") if w and w != prob.name]:
         pe = workloads.problem(name)
