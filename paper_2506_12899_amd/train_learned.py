@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--geometries", type=int, default=200)
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--iterates", default="0,3,8", help="Richardson steps before each sampled smoothing step")
+    ap.add_argument("--geometry", default="ellipsoid", choices=["ellipsoid", "union", "mixed"],
+                    help="training geometries: spheres/ellipsoids, 8-ball unions, or both alternating")
     ap.add_argument("--plain-form", action="store_true",
                     help="centre rule and per-level penalties instead of the stabilised 3D Q3 form")
     ap.add_argument("--draws", type=int, default=4)
@@ -81,8 +83,10 @@ def main():
         return Problem(geo, n, p, device=0, **opts)
 
     its = tuple(int(k) for k in args.iterates.split(","))
+    geom = {"ellipsoid": workloads.training_geometry, "union": workloads.training_union,
+            "mixed": lambda s: workloads.training_union(s) if s % 2 else workloads.training_geometry(s)}[args.geometry]
     data = learned.generate(factory, range(1, args.geometries + 1), args.n, 3, its, args.draws, device=dev,
-                            log=lambda m: None)
+                            log=lambda m: None, geometry=geom)
     t_data = time.time() - t0
     log(f"[train] {data[0].shape[0]} samples from {args.geometries} geometries in {t_data:.1f} s")
     net = learned.MLP(data[0].shape[1], data[1].shape[1], 64, device=dev, omega=0.8, train_uv=bool(args.train_uv))

@@ -96,6 +96,14 @@ def training_geometry(seed):
     return ellipsoid(c, rng.uniform(0.5, 0.85, 3), random_rotation(rng))
 
 
+def training_union(seed):
+    """Seeded union of 8 balls drawn like the 128^3 workload's (centres
+    U[-0.6, 0.6]^3, radii U[0.15, 0.35]) from default_rng(2000 + seed), for
+    training data with the creases of a union (seed 0 of `eight_balls` is
+    not among them)."""
+    return eight_balls(2000 + seed)
+
+
 def eight_balls(seed=0):
     rng = np.random.default_rng(seed)
     centers = rng.uniform(-0.6, 0.6, (8, 3))

@@ -216,3 +216,45 @@ def test_paper_setting_shift_extremes_match_fig3():
         assert abs(hi - phi_) <= 6e-5, (lam, lv, hi, phi_)
         if lam < 1.0:
             assert abs(lo - plo) <= 6e-5, (lam, lv, lo, plo)
+
+
+def test_deformed_domain_level_set_derivatives():
+    """The deformed domain of Sec. 5.4, phi = (1 - 3/4 sin^2(pi x)) (x^2 + y^2)
+    - 1/5, as the callback level set: its gradient and Hessian equal central
+    differences, and f = -Lap(phi + 1) equals the differenced Laplacian."""
+    from paper_2506_12899_amd import paper_mode
+    g = paper_mode.deformed_geometry()
+    sol = paper_mode.problem("deformed", 2, 3, 1, 0.5).solution
+    X = np.random.default_rng(4).uniform(-1, 1, (20, 2))
+    eps = 1e-5
+    E = np.eye(2) * eps
+    G = np.stack([(g.phi(X + E[c]) - g.phi(X - E[c])) / (2 * eps) for c in range(2)], axis=1)
+    assert np.abs(G - g.grad(X)).max() <= 1e-8
+    Hs = np.stack([(g.grad(X + E[c]) - g.grad(X - E[c])) / (2 * eps) for c in range(2)], axis=2)
+    assert np.abs(Hs - g.hess(X)).max() <= 1e-7
+    lap = sum((g.phi(X + E[c]) - 2 * g.phi(X) + g.phi(X - E[c])) / eps ** 2 for c in range(2))
+    assert np.abs(sol.f(X) + lap).max() <= 1e-4 * np.abs(lap).max()
+
+
+def test_deformed_domain_setup_matches_oracle():
+    """Sec. 5.4 domain in the paper setting (lambda = 0.5): the library's
+    active sets (volume fractions of a general level set) and its closest
+    points (Lagrangian Newton, Sec. 4.2) agree with the oracle's independent
+    construction on every level; every shift is normal to Gamma at its foot."""
+    from paper_2506_12899_amd import paper_mode
+    pr = paper_mode.problem("deformed", 2, 3, 2, 0.5)
+    pb = _problem(pr.geometry, pr.n, pr.p, **pr.opts)
+    og = oracle_geometry(pr.geometry)
+    okw = {k: v for k, v in pr.opts.items() if k in ("lo", "hi", "lambda_frac", "c_F", "c_G")}
+    for l in range(pb.n_levels):
+        info = pb.level_info(l)
+        L = dg.Level(og, 2, info["n"], info["p"], build_matrix=False, **okw)
+        assert np.array_equal(pb.active_cells(l), L.cells), l
+        sh = pb.shifts(l)
+        assert np.abs(sh - L.shifts).max() <= 1e-9, l
+        foot = (L.face_points + sh).reshape(-1, 2)
+        assert np.abs(og.phi(foot)).max() <= 1e-12
+        gr = pr.geometry.grad(foot)
+        d = sh.reshape(-1, 2)
+        cross = d[:, 0] * gr[:, 1] - d[:, 1] * gr[:, 0]
+        assert np.abs(cross).max() <= 1e-9 * np.abs(gr).max()
