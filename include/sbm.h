@@ -121,6 +121,10 @@ typedef struct {
                              setup (per level); no learned correction; transfers unfused  */
     int cheb_degree;      /* block-Jacobi updates per Chebyshev smoothing step (default 3)   */
     double cheb_range;    /* ratio of the interval's ends (default 20)                       */
+    int pencil;           /* 1 (default): on 3D Q2 and Q3 levels the interior cells (no surrogate
+                             face) go through a kernel with one lane per line of nodes, the
+                             boundary cells through the one-thread-per-DoF kernel; 0: all
+                             cells through the latter (same operator and update)          */
     int device;           /* HIP device ordinal (default 0); < 0 = host-only setup for tests:
                              no device data, the device entry points return SBM_EINVAL     */
     void *stream;         /* hipStream_t for all work (default NULL = null stream)            */
@@ -170,6 +174,12 @@ int sbm_active_cells(const struct sbm_problem *pb, int level, int *ijk, long lon
 int sbm_level_info(const struct sbm_problem *pb, int level, int *n, int *p, int *n_active,
                    int *n_colour0, int *n_surrogate_faces);
 int sbm_shifts(const struct sbm_problem *pb, int level, double *host_out, long long cap);
+/* Cell blocks of a level (for tests): boundary blocks (cells with a surrogate
+ * face), those whose inverse the singular-value floor changed (stab > 0,
+ * Sec. 3.1 stabilisation), and how many of the latter are colour-0 cells.
+ * Null outputs are skipped; level = -1 means the finest. */
+int sbm_level_blocks(const struct sbm_problem *pb, int level, int *n_boundary, int *n_clipped,
+                     int *n_clipped_colour0);
 
 /* Test hook: replace the shifts d of a level's surrogate Gauss points by
  * externally supplied ones (host, count = n_surrogate_faces x (p_l+1)^(dim-1)

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbm.so")
-SOURCES = ["refdata.cpp", "geometry.cpp", "setup.cpp", "kernels.hip", "solver.hip", "mlp.hip", "learned_api.hip"]
+SOURCES = ["refdata.cpp", "geometry.cpp", "setup.cpp", "kernels.hip", "pencil.hip", "solver.hip", "mlp.hip", "learned_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

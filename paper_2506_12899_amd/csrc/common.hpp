@@ -91,6 +91,7 @@ struct HostLevel {
     std::vector<double> Dint, Bint;  // nc*nc row-major, B = D^{-1}
     std::vector<double> Dbnd, Bbnd;  // n_bnd * nc*nc
     int n_clipped = 0;            // boundary blocks whose inverse the stabilisation changed
+    std::vector<char> clipped;    // n_bnd: 1 for those blocks
     // relation to the next coarser level (absent on level 0)
     int ratio = 1;                // 2 = h-transfer, 1 = p-transfer
     std::vector<int> parent;      // n_act -> coarse active index or -1
@@ -124,6 +125,19 @@ struct DevLevel {
     KRef<T> kref;
     // learned correction on this level (finest only), may be null
     T *lw = nullptr, *lU = nullptr, *lV = nullptr;  // n_bnd, n_bnd*nc*4, n_bnd*nc*4
+    // cells whose inverse the stabilisation changed (their block update does
+    // not zero the block residual): hold[n_bnd] flags their blocks; rep1 lists
+    // the colour-1 ones, clip0 the colour-0 ones with clip0_cbnd their block
+    // index on the next coarser level (p-transfers keep the cells)
+    int *hold = nullptr;
+    int *rep1 = nullptr, n_rep1 = 0;
+    int *clip0 = nullptr, *clip0_cbnd = nullptr, n_clip0 = 0;
+    // pencil path (3D levels it supports): interior cells in mesh order
+    // (whole-level operations) and by colour (n_int0 of colour 0 first), the
+    // boundary cells by colour (n_bl0 of colour 0 first) for the other kernel
+    bool pencil = false;
+    int *pen_all = nullptr, *pen_col = nullptr, *bnd_list = nullptr;
+    int n_int0 = 0, n_int1 = 0, n_bl0 = 0, n_bl1 = 0;
     // level work vectors (coarser levels and the FP32 cycle)
     T *z = nullptr, *b = nullptr, *r = nullptr;
     // Chebyshev-accelerated block-Jacobi smoother: search direction and the

@@ -21,6 +21,7 @@
 #include <type_traits>
 
 #include "kernels.hpp"
+#include "device_util.hpp"
 
 namespace sbm {
 
@@ -34,22 +35,6 @@ struct Sh {
     static constexpr int CPB = CPW * WAVES;
     static constexpr int NFACE = 2 * D;
 };
-
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    // blocks are dispatched round-robin over the 8 XCDs; give XCD x a contiguous range
-    int x = b & 7, q = nb >> 3, r = nb & 7;
-    return x * q + (x < r ? x : r) + (b >> 3);
-}
-
-// The threads of one cell always sit in one wave, so data exchanged through
-// LDS between them needs no block barrier: LDS instructions of a wave complete
-// in order, and this only keeps the compiler from moving memory operations
-// across the exchange point.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // DoF index of node (m along direction k, tangential index j) of a cell
 template <int D, int P>
@@ -270,6 +255,11 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
 #pragma unroll
             for (int j = 0; j < (PRE_B ? NC : 1); ++j) bcol[j] = Bt[(size_t)j * NC + i];
         }
+    }
+    // a held cell keeps its values to itself in this launch
+    bool held = false;
+    if constexpr (EMIT != EMIT_NONE) {
+        if (live && bi >= 0 && e.hold != nullptr) held = e.hold[bi] != 0;
     }
 
     // ---------------- volume + unshifted self terms (sum factorisation)
@@ -554,7 +544,9 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
             }
             xnew = su[lc][i] + R.omega * corr;
             out[(size_t)cell * NC + i] = xnew;
-            if constexpr (EMIT == EMIT_F64) e.z64[(size_t)cell * NC + i] = (double)xnew;
+            if constexpr (EMIT == EMIT_F64) {
+                if (!held) e.z64[(size_t)cell * NC + i] = (double)xnew;
+            }
         }
         if constexpr (EPRO) {
             // the cell's new values to all its lanes, then zf += E z (Sec. 3.2
@@ -562,7 +554,7 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
             wave_sync();
             if (live) sb[lc][i] = xnew;
             wave_sync();
-            if (efc >= 0) {
+            if (efc >= 0 && !held) {
                 const int o = EMIT == EMIT_H ? i : 0;
 #pragma unroll
                 for (int k = 0; k < NOUT; ++k) {
@@ -654,7 +646,10 @@ __attribute__((amdgpu_waves_per_eu(cell_min_waves<D, P, T, OP, EMIT>(), 8))) voi
     // remap gives every XCD a contiguous range of cells.
     const int bb = xcd_remap(blockIdx.x, gridDim.x);
     int bstart, bend;
-    if (a.batch_start != nullptr) {
+    if (a.perm != nullptr) {
+        bstart = bb * CPB;
+        bend = ncells;
+    } else if (a.batch_start != nullptr) {
         bstart = a.batch_start[bb];
         bend = min(bstart + CPB, bstart < a.split ? a.split : cell0 + ncells);
     } else {
@@ -662,7 +657,7 @@ __attribute__((amdgpu_waves_per_eu(cell_min_waves<D, P, T, OP, EMIT>(), 8))) voi
         bend = cell0 + ncells;
     }
     cell_batch<D, P, T, OP, S::WAVES, EMIT, typename EmitParam<T, EMIT>::type, NoHook, decltype(stage)>(
-        L, sB, bstart, bend, xin, out, b, a, sR, nullptr, e, sP, NoHook(), stage);
+        L, sB, bstart, bend, xin, out, b, a, sR, a.perm, e, sP, NoHook(), stage);
 }
 
 // Residual and restriction in one launch (Sec. 3.2: the restriction is the
@@ -672,7 +667,8 @@ __attribute__((amdgpu_waves_per_eu(cell_min_waves<D, P, T, OP, EMIT>(), 8))) voi
 //    that the children of a coarse cell sit in one wave; their residuals stay
 //    in LDS and the wave forms bc = sum_o E_o^T r_o.
 //  p-transfer (same cells, perm = nullptr): batches follow the whole-level
-//    batch table and every cell restricts its own residual.
+//    batch table and every cell restricts its own residual; or, with nch = 1
+//    and perm = grp a list of cells, only those cells.
 // (occupancy floor as for the cell kernels: the 3D Q2 FP64 form fits 3 waves
 // per SIMD without spilling but is otherwise allocated 169 VGPRs, 2 waves; the
 // 3D Q3 FP32 form fits 78 VGPRs, 6 waves, instead of 122)
@@ -806,10 +802,14 @@ static int launch_rr(int n_coarse, int nch, int n1c, const int *perm, const int 
     if (c1_only && (perm != nullptr || a.split < 0 || a.split > n_coarse)) return -1;
     ZeroStartArgs<T> zs{};
     if (zsp != nullptr) {
-        // the zero-start update is sized for Q1 -> Q1 (h) and Q(P) -> Q(P-1) (p)
-        const bool h = perm != nullptr;
-        if ((h ? (P != 1 || n1c != 2 || zsp->grp_bnd == nullptr) : (P < 2 || n1c != P)) || zsp->z == nullptr ||
-            zsp->bnd_of == nullptr || zsp->Bint_t == nullptr || zsp->split < 0 || zsp->split > n_coarse)
+        // the zero-start update is sized for Q1 -> Q1 (h) and Q(P) -> Q(P-1) (p);
+        // with a cell list the coarse blocks come per group
+        const bool h = nch != 1;
+        const bool listed = !h && perm != nullptr;   // n_coarse counts the listed cells
+        if ((h ? (P != 1 || n1c != 2) : (P < 2 || n1c != P)) || (perm != nullptr && zsp->grp_bnd == nullptr) ||
+            zsp->z == nullptr ||
+            zsp->bnd_of == nullptr || zsp->Bint_t == nullptr || zsp->split < 0 ||
+            (!listed && zsp->split > n_coarse))
             return -1;
         zs = *zsp;
     }
@@ -851,7 +851,7 @@ static int launch_dp(int op, int cell0, int ncells, const T *x, T *y, const T *b
                      const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e) {
     if (ncells <= 0) return 0;
     using S = Sh<D, P>;
-    int nb = a.batch_start != nullptr ? a.nbatch : (ncells + S::CPB - 1) / S::CPB;
+    int nb = a.perm == nullptr && a.batch_start != nullptr ? a.nbatch : (ncells + S::CPB - 1) / S::CPB;
     const dim3 g(nb), bl(64 * S::WAVES);
     const int kind = e != nullptr ? e->kind : EMIT_NONE;
     if (op != OP_SMOOTH && kind != EMIT_NONE) return -1;

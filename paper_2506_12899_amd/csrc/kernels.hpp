@@ -21,6 +21,9 @@ struct CellArgs {
     // the contiguous range of batches an XCD receives is one spatial region.
     const int *batch_start;
     int nbatch, split;
+    // Optional cell list: the launch treats the cells perm[0 .. ncells)
+    // instead of a contiguous range or the batch table
+    const int *perm;
 };
 
 // waves per block of the cell kernels for cells of nc DoFs (measured: two
@@ -51,6 +54,9 @@ struct EmitArgs {
     T *zf;                    // EMIT_H / EMIT_P: fine-level vector, zf += P z
     double *z64;              // EMIT_F64: receives z in FP64
     T P1[2][MAXN1][MAXN1];    // 1D embedding [child offset][fine node][coarse node]
+    // optional, per boundary block of the updated level: nonzero = this launch
+    // does not send the cell's values on (a later launch updates it again)
+    const int *hold;
 };
 
 // First colour-0 update of the coarser level from z = 0, formed by the
@@ -65,6 +71,14 @@ struct ZeroStartArgs {
     int split;                // coarse cells of colour 0
     T omega;
 };
+
+// Interior cells of a level by the pencil kernel (pencil.hip): OP_APPLY,
+// OP_RESID or OP_SMOOTH on the cells cells[0 .. ncells), all of which must
+// have every face neighbour; e: null or EMIT_F64.  Levels it handles:
+bool pencil_supported(int d, int p);
+template <typename T>
+int launch_pencil(int d, int p, int op, int ncells, const int *cells, const T *x, T *y, const T *b,
+                  const CellArgs<T> &a, const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e);
 
 template <typename T>
 int launch_cellop(int d, int p, int op, int cell0, int ncells, const T *x, T *y, const T *b, const CellArgs<T> &a,

@@ -1,0 +1,413 @@
+// Pencil form of the cell operator on the interior cells of 3D levels
+// (operator of Sec. 2.2, cell-wise block update of Sec. 3.1).
+//
+// An interior cell has all 2d face neighbours, hence no surrogate face: its 1D
+// self operator is the interior one T in every direction, and its block
+// inverse is the level's shared one.  On such a cell, in reference units and
+// scaled by h^(d-2),
+//   (A u)_K = sum_k (prod_{d != k} M_d) (T_k u_K + E_k f_k)
+// where f_k holds the SIPG face data of the two neighbours across the faces
+// normal to e_k, at each face node: va = -sg dn / 2 - sigma_F t and vb = t / 2
+// from the neighbour's trace t and normal derivative dn (sg = -1 on the low
+// face, +1 on the high one), and E_k places them along e_k: va on the end node
+// of that face, sg vb times the derivative of the basis there.  So every face
+// term is a source of the contraction stage of its normal direction.
+//
+// Thread mapping: (P+1)^2 lanes per cell, each holding one line of P+1 nodes
+// (a pencil): along x in the first stage (A = M_x u, B = T_x u + E_x f_x),
+// along y in the second (Q = M_y A, R = T_y A + M_y B + E_y M_x f_y), along z
+// in the third (y = M_z R + T_z Q + E_z M_y M_x f_z).  The direction changes
+// and the tangential contractions of the y and z face data go through LDS;
+// every other coefficient index is a compile-time constant, so the 1D
+// operators come from the kernel arguments (scalar registers).  A cell's lanes
+// share a wave, so its LDS exchanges need no block barrier.  Against the
+// one-thread-per-DoF kernel this removes the per-DoF index arithmetic and most
+// LDS reads, which bound that kernel's instruction issue on 64-DoF cells.
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "device_util.hpp"
+
+namespace sbm {
+
+template <int P>
+struct PSh {
+    static constexpr int N1 = P + 1, NP = N1 * N1, NC = NP * N1;
+    static constexpr int CPW = 64 / NP;      // cells per wave
+    static constexpr int WAVES = 4;          // waves per block
+    static constexpr int CPB = CPW * WAVES;  // cells per block
+};
+
+template <int P, typename T>
+struct PencilLds {
+    static constexpr int CPB = PSh<P>::CPB, NC = PSh<P>::NC, NP = PSh<P>::NP;
+    T v0[CPB][NC];         // A, then Q, then (smoother) the residual
+    T v1[CPB][NC];         // B, then R
+    T fa[CPB][2][2][NP];   // face data [side][va, vb][face node]
+    T fg[CPB][2][2][NP];   // z-face data after the x contraction
+};
+
+// face data of one neighbour line (its nodes along the face normal, from the
+// far end to the shared face or back): va, vb as above; s = side of the cell
+template <int P, typename T>
+__device__ __forceinline__ void face_data(const KRef<T> &R, int s, const T *line, T &va, T &vb) {
+    constexpr int N1 = P + 1;
+    const T *gN = R.g[s == 1 ? 0 : 1];   // the neighbour's derivative at the shared face
+    const T t = line[s == 1 ? 0 : P];
+    T dn = 0;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) dn += gN[m] * line[m];
+    const T sg = s == 1 ? T(1) : T(-1);
+    va = T(-0.5) * sg * dn - R.sigF * t;
+    vb = T(0.5) * t;
+}
+
+// pencil += E_s (va, vb): va on the end node of side s, sg vb g_s along the line
+template <int P, typename T>
+__device__ __forceinline__ void inject(const KRef<T> &R, int s, T va, T vb, T *v) {
+    constexpr int N1 = P + 1;
+    const T sg = s == 1 ? T(1) : T(-1);
+    v[s == 1 ? P : 0] += va;
+#pragma unroll
+    for (int c = 0; c < N1; ++c) v[c] += sg * R.g[s][c] * vb;
+}
+
+// entry a of a row-major N1 x N1 table at a lane-dependent row, by selects
+// (an indexed kernel-argument read would go through scratch memory)
+template <int N1, typename T>
+__device__ __forceinline__ T row_entry(const T (&M)[MAXN1][MAXN1], int row, int a) {
+    T v = M[0][a];
+#pragma unroll
+    for (int r = 1; r < N1; ++r) v = row == r ? M[r][a] : v;
+    return v;
+}
+
+// OP_APPLY: out = A x; OP_RESID: out = b - A x; OP_SMOOTH: x (= out) += omega
+// B_int (b - A x) on the listed cells (F64OUT: the new values also go to z64).
+// cells[0 .. ncells): interior cells of the level.
+template <int P, typename T, int OP, bool F64OUT>
+__global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, const int *__restrict__ cells,
+                                                                     const T *xin, T *out, const T *__restrict__ b,
+                                                                     const int *__restrict__ nbr,
+                                                                     const T *__restrict__ Bint_t, KRef<T> R,
+                                                                     double *__restrict__ z64) {
+    using S = PSh<P>;
+    constexpr int N1 = S::N1, NP = S::NP, NC = S::NC, CPW = S::CPW;
+    constexpr bool FULL = CPW * NP == 64;
+    // the smoother's shared inverse in LDS, laid out [j][q][c] (the lane's N1
+    // outputs q + NP c next to each other); FP32 only (FP64: 32 KB per block
+    // would halve the occupancy, its columns come from memory)
+    constexpr bool SBL = OP == OP_SMOOTH && sizeof(T) == 4;
+    __shared__ PencilLds<P, T> L;
+    __shared__ T sB[SBL ? NC * NC : 1];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = lane / NP;
+    const bool inslot = FULL || slot < CPW;
+    const int q = inslot ? lane - slot * NP : 0;
+    const int qa = q % N1, qb = q / N1;
+    const int lc = wave * CPW + (inslot ? slot : 0);
+    const int pos = xcd_remap(blockIdx.x, gridDim.x) * S::CPB + lc;
+    const bool live = inslot && pos < ncells;
+
+    // ---- loads: the staged inverse, the cell's own data and its neighbour indices
+    constexpr int NT = 64 * S::WAVES;
+    constexpr int SPER = SBL ? (NC * NC + NT - 1) / NT : 1;
+    T sbv[SPER];
+    if constexpr (SBL) {
+#pragma unroll
+        for (int k = 0; k < SPER; ++k) {
+            const int t = (int)threadIdx.x + k * NT;   // destination index [j][qq][c]
+            const int j = t / NC, rem = t % NC, qq = rem / N1, c = rem % N1;
+            sbv[k] = t < NC * NC ? Bint_t[(size_t)j * NC + qq + NP * c] : T(0);
+        }
+    }
+    const int cell = live ? cells[pos] : 0;
+    const T *xc = xin + (size_t)cell * NC;
+    T u[N1], bv[N1], xz[N1];
+#pragma unroll
+    for (int m = 0; m < N1; ++m) u[m] = xc[m + N1 * q];
+    if constexpr (OP != OP_APPLY) {
+#pragma unroll
+        for (int c = 0; c < N1; ++c) bv[c] = b[(size_t)cell * NC + q + NP * c];
+    }
+    if constexpr (OP == OP_SMOOTH) {
+#pragma unroll
+        for (int c = 0; c < N1; ++c) xz[c] = xc[q + NP * c];
+    }
+    int nb[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int v = live ? nbr[(size_t)cell * 6 + f] : cell;
+        nb[f] = v >= 0 ? v : cell;   // (listed cells have all six; clamped all the same)
+    }
+    T Ma[N1], Mb[N1];
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+        Ma[m] = row_entry<N1>(R.M, qa, m);
+        Mb[m] = row_entry<N1>(R.M, qb, m);
+    }
+    // neighbour lines through this lane's face nodes: x faces at (y, z) = (qa,
+    // qb), y faces at (x, z) = (qa, qb), z faces at (x, y) = (qa, qb)
+    T xl[2][N1], yl[2][N1], zl[2][N1];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const T *nx = xin + (size_t)nb[s] * NC;
+        const T *ny = xin + (size_t)nb[2 + s] * NC;
+        const T *nz = xin + (size_t)nb[4 + s] * NC;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            xl[s][m] = nx[m + N1 * q];
+            yl[s][m] = ny[qa + N1 * m + NP * qb];
+            zl[s][m] = nz[qa + N1 * qb + NP * m];
+        }
+    }
+    if constexpr (SBL) {
+#pragma unroll
+        for (int k = 0; k < SPER; ++k) {
+            const int t = (int)threadIdx.x + k * NT;
+            if (t < NC * NC) sB[t] = sbv[k];
+        }
+    }
+
+    // ---- stage x: A = M u, B = T u + E_x f_x along x at (y, z) = (qa, qb)
+    T A[N1], B[N1];
+#pragma unroll
+    for (int c = 0; c < N1; ++c) {
+        T a = 0, bb = 0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            a += R.M[c][m] * u[m];
+            bb += R.Tv[0][c][m] * u[m];
+        }
+        A[c] = a;
+        B[c] = bb;
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        T va, vb;
+        face_data<P>(R, s, xl[s], va, vb);
+        inject<P>(R, s, va, vb, B);
+    }
+    if (inslot) {
+#pragma unroll
+        for (int c = 0; c < N1; ++c) {
+            L.v0[lc][c + N1 * q] = A[c];
+            L.v1[lc][c + N1 * q] = B[c];
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            T va, vb;
+            face_data<P>(R, s, yl[s], va, vb);
+            L.fa[lc][s][0][q] = va;
+            L.fa[lc][s][1][q] = vb;
+        }
+    }
+    wave_sync();
+
+    // ---- stage y: along y at (x, z) = (qa, qb)
+    T Qv[N1], Rv[N1];
+    {
+        T a[N1], bb[N1];
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            a[m] = L.v0[lc][qa + N1 * m + NP * qb];
+            bb[m] = L.v1[lc][qa + N1 * m + NP * qb];
+        }
+#pragma unroll
+        for (int c = 0; c < N1; ++c) {
+            T t1 = 0, t2 = 0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) {
+                t1 += R.M[c][m] * a[m];
+                t2 += R.Tv[0][c][m] * a[m] + R.M[c][m] * bb[m];
+            }
+            Qv[c] = t1;
+            Rv[c] = t2;
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            // y-face data contracted along x at face node (x, z) = (qa, qb)
+            T fa = 0, fb = 0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) {
+                fa += Ma[m] * L.fa[lc][s][0][m + N1 * qb];
+                fb += Ma[m] * L.fa[lc][s][1][m + N1 * qb];
+            }
+            inject<P>(R, s, fa, fb, Rv);
+        }
+    }
+    wave_sync();
+    if (inslot) {
+#pragma unroll
+        for (int c = 0; c < N1; ++c) {
+            L.v0[lc][qa + N1 * c + NP * qb] = Qv[c];
+            L.v1[lc][qa + N1 * c + NP * qb] = Rv[c];
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            T va, vb;
+            face_data<P>(R, s, zl[s], va, vb);
+            L.fa[lc][s][0][q] = va;
+            L.fa[lc][s][1][q] = vb;
+        }
+    }
+    wave_sync();
+    // z-face data contracted along x, at face node (x, y) = (qa, qb)
+    {
+        T g[2][2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                T acc = 0;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) acc += Ma[m] * L.fa[lc][s][w][m + N1 * qb];
+                g[s][w] = acc;
+            }
+        if (inslot) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int w = 0; w < 2; ++w) L.fg[lc][s][w][q] = g[s][w];
+        }
+    }
+    wave_sync();
+
+    // ---- stage z: along z at (x, y) = (qa, qb); DoF q + NP c
+    T y[N1];
+    {
+        T qv[N1], rv[N1];
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            qv[m] = L.v0[lc][q + NP * m];
+            rv[m] = L.v1[lc][q + NP * m];
+        }
+#pragma unroll
+        for (int c = 0; c < N1; ++c) {
+            T t = 0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) t += R.M[c][m] * rv[m] + R.Tv[0][c][m] * qv[m];
+            y[c] = t;
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            // and along y
+            T fa = 0, fb = 0;
+#pragma unroll
+            for (int m = 0; m < N1; ++m) {
+                fa += Mb[m] * L.fg[lc][s][0][qa + N1 * m];
+                fb += Mb[m] * L.fg[lc][s][1][qa + N1 * m];
+            }
+            inject<P>(R, s, fa, fb, y);
+        }
+#pragma unroll
+        for (int c = 0; c < N1; ++c) y[c] *= R.scale;
+    }
+
+    // ---- output
+    T *oc = out + (size_t)cell * NC;
+    if constexpr (OP == OP_APPLY) {
+        if (live) {
+#pragma unroll
+            for (int c = 0; c < N1; ++c) oc[q + NP * c] = y[c];
+        }
+    } else if constexpr (OP == OP_RESID) {
+        if (live) {
+#pragma unroll
+            for (int c = 0; c < N1; ++c) oc[q + NP * c] = bv[c] - y[c];
+        }
+    } else {
+        wave_sync();   // the z stage has read v0
+        if (inslot) {
+#pragma unroll
+            for (int c = 0; c < N1; ++c) L.v0[lc][q + NP * c] = bv[c] - y[c];
+        }
+        wave_sync();
+        if constexpr (SBL) __syncthreads();   // the staged inverse
+        T corr[N1];
+#pragma unroll
+        for (int c = 0; c < N1; ++c) corr[c] = 0;
+        if constexpr (SBL) {
+#pragma unroll 8
+            for (int j = 0; j < NC; ++j) {
+                const T r = L.v0[lc][j];
+#pragma unroll
+                for (int c = 0; c < N1; ++c) corr[c] += sB[(j * NP + q) * N1 + c] * r;
+            }
+        } else {
+            // columns of B_int^T in groups of JB loads in flight
+            constexpr int JB = NC % 8 == 0 ? 8 : (NC % 9 == 0 ? 9 : 1);
+#pragma unroll 1
+            for (int j0 = 0; j0 < NC; j0 += JB) {
+                T col[JB][N1];
+#pragma unroll
+                for (int jj = 0; jj < JB; ++jj)
+#pragma unroll
+                    for (int c = 0; c < N1; ++c) col[jj][c] = Bint_t[(size_t)(j0 + jj) * NC + q + NP * c];
+#pragma unroll
+                for (int jj = 0; jj < JB; ++jj) {
+                    const T r = L.v0[lc][j0 + jj];
+#pragma unroll
+                    for (int c = 0; c < N1; ++c) corr[c] += col[jj][c] * r;
+                }
+            }
+        }
+        if (live) {
+#pragma unroll
+            for (int c = 0; c < N1; ++c) {
+                const T xn = xz[c] + R.omega * corr[c];
+                oc[q + NP * c] = xn;
+                if constexpr (F64OUT) z64[(size_t)cell * NC + q + NP * c] = (double)xn;
+            }
+        }
+    }
+}
+
+template <int P, typename T>
+static int launch_p(int op, int ncells, const int *cells, const T *x, T *y, const T *b, const CellArgs<T> &a,
+                    const KRef<T> &R, hipStream_t st, double *z64) {
+    using S = PSh<P>;
+    const dim3 g((ncells + S::CPB - 1) / S::CPB), bl(64 * S::WAVES);
+    if (op == OP_APPLY)
+        hipLaunchKernelGGL((pencil_kernel<P, T, OP_APPLY, false>), g, bl, 0, st, ncells, cells, x, y, b, a.nbr,
+                           a.Bint_t, R, nullptr);
+    else if (op == OP_RESID)
+        hipLaunchKernelGGL((pencil_kernel<P, T, OP_RESID, false>), g, bl, 0, st, ncells, cells, x, y, b, a.nbr,
+                           a.Bint_t, R, nullptr);
+    else if (op == OP_SMOOTH && z64 == nullptr)
+        hipLaunchKernelGGL((pencil_kernel<P, T, OP_SMOOTH, false>), g, bl, 0, st, ncells, cells, x, y, b, a.nbr,
+                           a.Bint_t, R, nullptr);
+    else if (op == OP_SMOOTH) {
+        if constexpr (std::is_same<T, float>::value)
+            hipLaunchKernelGGL((pencil_kernel<P, T, OP_SMOOTH, true>), g, bl, 0, st, ncells, cells, x, y, b, a.nbr,
+                               a.Bint_t, R, z64);
+        else
+            return -1;
+    } else {
+        return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+bool pencil_supported(int d, int p) { return d == 3 && (p == 2 || p == 3); }
+
+template <typename T>
+int launch_pencil(int d, int p, int op, int ncells, const int *cells, const T *x, T *y, const T *b,
+                  const CellArgs<T> &a, const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e) {
+    if (ncells <= 0) return 0;
+    if (!pencil_supported(d, p) || cells == nullptr) return -1;
+    double *z64 = nullptr;
+    if (e != nullptr) {
+        if (e->kind != EMIT_F64 || op != OP_SMOOTH || e->z64 == nullptr) return -1;
+        z64 = e->z64;
+    }
+    return p == 3 ? launch_p<3, T>(op, ncells, cells, x, y, b, a, R, st, z64)
+                  : launch_p<2, T>(op, ncells, cells, x, y, b, a, R, st, z64);
+}
+template int launch_pencil<double>(int, int, int, int, const int *, const double *, double *, const double *,
+                                   const CellArgs<double> &, const KRef<double> &, hipStream_t,
+                                   const EmitArgs<double> *);
+template int launch_pencil<float>(int, int, int, int, const int *, const float *, float *, const float *,
+                                  const CellArgs<float> &, const KRef<float> &, hipStream_t, const EmitArgs<float> *);
+
+}  // namespace sbm

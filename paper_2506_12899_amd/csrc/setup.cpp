@@ -548,6 +548,7 @@ int build_blocks(HostLevel &L, const sbm_options &o, std::string &err) {
         return SBM_ESINGULAR;
     }
     L.n_clipped = 0;
+    L.clipped.assign(L.n_bnd, 0);
     if (o.stab > 0.0) {
         // floor = stab * (smallest singular value of the interior block); a
         // block needs the SVD only if 1 / |B_K|_F < floor (sigma_min >= 1/|B|_F)
@@ -558,7 +559,10 @@ int build_blocks(HostLevel &L, const sbm_options &o, std::string &err) {
             double f2 = 0;
             for (int t = 0; t < nc * nc; ++t) f2 += B[t] * B[t];
             if (1.0 / std::sqrt(f2) >= floor_) return;
-            if (clipped_inverse(&L.Dbnd[(size_t)b * nc * nc], nc, floor_, B)) nclip++;
+            if (clipped_inverse(&L.Dbnd[(size_t)b * nc * nc], nc, floor_, B)) {
+                L.clipped[b] = 1;
+                nclip++;
+            }
         });
         L.n_clipped = nclip;
     }

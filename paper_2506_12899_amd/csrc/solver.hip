@@ -95,6 +95,41 @@ void cast_kref(const KRef<double> &a, KRef<T> &b) {
     b.ext = a.ext;
 }
 
+// The cells of level l whose inverse the stabilisation changed, by colour
+// (buffers sized n_bnd, allocated once; set_shifts refills them)
+template <typename T>
+int clip_lists(sbm_problem *pb, int l, DevLevel<T> &D, bool alloc) {
+    const HostLevel &L = pb->levels[l];
+    int rc;
+    if (alloc) {
+        if ((rc = dalloc(pb, &D.hold, L.n_bnd)) || (rc = dalloc(pb, &D.rep1, L.n_bnd)) ||
+            (rc = dalloc(pb, &D.clip0, L.n_bnd)) || (rc = dalloc(pb, &D.clip0_cbnd, L.n_bnd)))
+            return rc;
+    }
+    std::vector<int> hold(L.n_bnd, 0), rep1, clip0, cbnd;
+    const bool ptransfer = l > 0 && L.ratio == 1;
+    for (int K = 0; K < L.n_act; ++K) {
+        const int bi = L.bnd_of[K];
+        if (bi < 0 || (size_t)bi >= L.clipped.size() || !L.clipped[bi]) continue;
+        hold[bi] = 1;
+        if (K >= L.n_col0) {
+            rep1.push_back(K);
+        } else {
+            clip0.push_back(K);
+            cbnd.push_back(ptransfer ? pb->levels[l - 1].bnd_of[K] : -1);
+        }
+    }
+    D.n_rep1 = (int)rep1.size();
+    D.n_clip0 = (int)clip0.size();
+    if (L.n_bnd > 0) HIPCHK(hipMemcpy(D.hold, hold.data(), hold.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!rep1.empty()) HIPCHK(hipMemcpy(D.rep1, rep1.data(), rep1.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!clip0.empty()) {
+        HIPCHK(hipMemcpy(D.clip0, clip0.data(), clip0.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(D.clip0_cbnd, cbnd.data(), cbnd.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    return SBM_OK;
+}
+
 template <typename T>
 int upload_level(sbm_problem *pb, int l, DevLevel<T> &D) {
     const HostLevel &L = pb->levels[l];
@@ -110,6 +145,33 @@ int upload_level(sbm_problem *pb, int l, DevLevel<T> &D) {
     if ((rc = upload(pb, &D.nbr, L.nbr.data(), L.nbr.size()))) return rc;
     if ((rc = upload(pb, &D.bnd_of, L.bnd_of.data(), L.bnd_of.size()))) return rc;
     if ((rc = upload(pb, &D.bnd_cells, L.bnd_cells.data(), L.bnd_cells.size()))) return rc;
+    if ((rc = clip_lists(pb, l, D, true))) return rc;
+    if (pb->opt.pencil && pencil_supported(L.d, L.p)) {
+        std::vector<int> col, all, bl;
+        for (int c = 0; c < 2; ++c) {
+            const int k0 = c == 0 ? 0 : L.n_col0, k1 = c == 0 ? L.n_col0 : L.n_act;
+            for (int K = k0; K < k1; ++K) (L.bnd_of[K] < 0 ? col : bl).push_back(K);
+            if (c == 0) {
+                D.n_int0 = (int)col.size();
+                D.n_bl0 = (int)bl.size();
+            }
+        }
+        D.n_int1 = (int)col.size() - D.n_int0;
+        D.n_bl1 = (int)bl.size() - D.n_bl0;
+        // mesh (lexicographic) order for whole-level operations: a cell's
+        // neighbours, of the other colour, are then near it in the launch
+        all = col;
+        auto key = [&](int K) {
+            long long v = 0;
+            for (int c = L.d - 1; c >= 0; --c) v = v * L.n + L.cells[(size_t)K * L.d + c];
+            return v;
+        };
+        std::sort(all.begin(), all.end(), [&](int x, int y) { return key(x) < key(y); });
+        if ((rc = upload(pb, &D.pen_all, all.data(), all.size())) || (rc = upload(pb, &D.pen_col, col.data(), col.size())) ||
+            (rc = upload(pb, &D.bnd_list, bl.data(), bl.size())))
+            return rc;
+        D.pencil = true;
+    }
     {
         // whole-level batches, the two colours merged by relative position
         const int cpb = cells_per_block(L.d, L.p);
@@ -206,6 +268,7 @@ CellArgs<T> cell_args(const DevLevel<T> &D, bool learned) {
     a.batch_start = nullptr;
     a.nbatch = 0;
     a.split = D.n_col0;
+    a.perm = nullptr;
     return a;
 }
 
@@ -220,6 +283,13 @@ template <typename T>
 int level_apply(sbm_problem *pb, int l, int op, const T *x, T *y, const T *b) {
     auto &D = devlevels<T>(pb)[l];
     CellArgs<T> a = cell_args(D, false);
+    if (D.pencil) {
+        // interior cells by the pencil kernel, boundary cells by the cell kernel
+        KCHK(launch_pencil<T>(D.d, D.p, op, D.n_int0 + D.n_int1, D.pen_all, x, y, b, a, D.kref, pb->stream, nullptr));
+        a.perm = D.bnd_list;
+        KCHK(launch_cellop<T>(D.d, D.p, op, 0, D.n_bl0 + D.n_bl1, x, y, b, a, D.kref, pb->stream));
+        return SBM_OK;
+    }
     a.batch_start = D.batch_start;
     a.nbatch = D.nbatch;
     KCHK(launch_cellop<T>(D.d, D.p, op, 0, D.n_act, x, y, b, a, D.kref, pb->stream));
@@ -233,7 +303,28 @@ int colour_update(sbm_problem *pb, int l, int colour, const T *b, T *z, const Em
     int c0 = colour == 0 ? 0 : D.n_col0;
     int nc = colour == 0 ? D.n_col0 : D.n_act - D.n_col0;
     bool learned = pb->learned_on && D.lw != nullptr && l == (int)pb->levels.size() - 1;
+    if (D.pencil && (em == nullptr || em->kind == EMIT_F64)) {
+        // the learned correction acts on boundary cells only
+        CellArgs<T> a = cell_args(D, learned);
+        KCHK(launch_pencil<T>(D.d, D.p, OP_SMOOTH, colour == 0 ? D.n_int0 : D.n_int1,
+                              D.pen_col + (colour == 0 ? 0 : D.n_int0), z, z, b, a, D.kref, pb->stream, em));
+        a.perm = D.bnd_list + (colour == 0 ? 0 : D.n_bl0);
+        KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, 0, colour == 0 ? D.n_bl0 : D.n_bl1, z, z, b, a, D.kref,
+                              pb->stream, em));
+        return SBM_OK;
+    }
     KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, c0, nc, z, z, b, cell_args(D, learned), D.kref, pb->stream, em));
+    return SBM_OK;
+}
+
+// the block update on the listed cells of level l only (no learned correction)
+template <typename T>
+int list_update(sbm_problem *pb, int l, const int *cells, int count, const T *b, T *z,
+                const EmitArgs<T> *em = nullptr) {
+    auto &D = devlevels<T>(pb)[l];
+    CellArgs<T> a = cell_args(D, false);
+    a.perm = cells;
+    KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, 0, count, z, z, b, a, D.kref, pb->stream, em));
     return SBM_OK;
 }
 
@@ -285,16 +376,25 @@ int resid_restrict(sbm_problem *pb, int l, const T *z, const T *b, T *bc, T *zc 
         zs.split = Dc.n_col0;
         zs.omega = Dc.kref.omega;
     }
-    // After a smoothing step that ends with an exact colour-0 block solve
-    // (omega = 1, unshifted inverses, no learned correction on this level) the
-    // colour-0 residual is zero up to rounding: a p-transfer then computes only
-    // colour 1 (the cells map one to one, so the colour-0 part of bc is zero).
+    // After a smoothing step that ends with a colour-0 block solve (omega = 1,
+    // unshifted inverses, no learned correction on this level) the colour-0
+    // residual is zero up to rounding on every cell whose inverse is exact: a
+    // p-transfer then computes colour 1 (the cells map one to one, so the
+    // colour-0 part of bc is zero) and, in a second launch, the colour-0 cells
+    // whose inverse the stabilisation changed.
     const bool learned_here = pb->learned_on && l == (int)pb->levels.size() - 1 && Df.lw != nullptr;
     const bool c1_only = nch == 1 && pb->opt.smoother == 0 && pb->opt.nu_pre > 0 && pb->opt.omega == 1.0 &&
-                         pb->opt.allow_singular == 0 && pb->levels[l].n_clipped == 0 && !learned_here;
+                         pb->opt.allow_singular == 0 && !learned_here &&
+                         (pb->levels[l].n_clipped == 0 || Df.hold != nullptr);
     KCHK(launch_resid_restrict<T>(Df.d, Df.p, Dc.n_act, nch, Dc.p + 1, nch == 1 ? nullptr : Df.rr_perm,
                                   nch == 1 ? nullptr : Df.rr_grp, z, b, bc, ca, Df.kref, tr, pb->stream,
                                   zc != nullptr ? &zs : nullptr, c1_only));
+    if (c1_only && Df.n_clip0 > 0) {
+        ZeroStartArgs<T> zl = zs;
+        zl.grp_bnd = Df.clip0_cbnd;
+        KCHK(launch_resid_restrict<T>(Df.d, Df.p, Df.n_clip0, 1, Dc.p + 1, Df.clip0, Df.clip0, z, b, bc, ca, Df.kref,
+                                      tr, pb->stream, zc != nullptr ? &zl : nullptr, false));
+    }
     return SBM_OK;
 }
 
@@ -308,13 +408,14 @@ int prolong_add(sbm_problem *pb, int l, const T *zc, T *zf) {
     return SBM_OK;
 }
 
-// One SSOR step: colours 0, 1, 1, 0.  With omega = 1 and the exact cell
-// inverses, the first colour-1 update zeroes the residual of every colour-1
-// cell, and nothing it depends on changes before the repeated colour-1 update
-// (cells of one colour do not couple), so that update adds zero up to rounding
-// and is skipped.  With omega != 1, inexact inverses (allow_singular: every
-// block is then (D_K + eps I)^-1; stabilised blocks of the level) or the
-// learned correction it is kept.
+// One SSOR step: colours 0, 1, 1, 0.  With omega = 1, the first colour-1
+// update zeroes the residual of every colour-1 cell whose inverse is exact,
+// and nothing it depends on changes before the repeated colour-1 update (cells
+// of one colour do not couple), so the repeat adds zero there up to rounding:
+// it runs only on the colour-1 cells whose inverse the stabilisation changed
+// (none: it is skipped), and the first update holds back their emission.
+// With omega != 1, allow_singular (every block is then (D_K + eps I)^-1) or
+// the learned correction the full repeat is kept.
 // from_zero: z starts at zero; with b64 (FP32 cycle only) the right-hand side
 // is read in FP64 and its FP32 copy written to b on the way.  started: that
 // first colour-0 update from zero was already formed (by the finer level's
@@ -324,8 +425,11 @@ template <typename T>
 int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false, const double *b64 = nullptr,
               bool started = false, const EmitArgs<T> *em = nullptr) {
     const bool learned_here = pb->learned_on && l == (int)pb->levels.size() - 1;
-    const bool skip_repeat = pb->opt.omega == 1.0 && pb->opt.allow_singular == 0 && pb->levels[l].n_clipped == 0 &&
-                             !learned_here;
+    auto &DL = devlevels<T>(pb)[l];
+    const bool exact_repeat = pb->opt.omega == 1.0 && pb->opt.allow_singular == 0 && !learned_here &&
+                              (pb->levels[l].n_clipped == 0 || DL.hold != nullptr);
+    const bool skip_repeat = exact_repeat && DL.n_rep1 == 0;
+    const bool list_repeat = exact_repeat && DL.n_rep1 > 0;
     int rc;
     if (started) {
         // nothing: z holds the zero-start colour-0 update
@@ -342,8 +446,18 @@ int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false, 
     } else if ((rc = colour_update<T>(pb, l, 0, b, z))) {
         return rc;
     }
-    if (!skip_repeat && (rc = colour_update<T>(pb, l, 1, b, z))) return rc;
-    if ((rc = colour_update<T>(pb, l, 1, b, z, em))) return rc;
+    if (list_repeat) {
+        EmitArgs<T> eh{};
+        if (em != nullptr) {
+            eh = *em;
+            eh.hold = DL.hold;
+        }
+        if ((rc = colour_update<T>(pb, l, 1, b, z, em != nullptr ? &eh : nullptr))) return rc;
+        if ((rc = list_update<T>(pb, l, DL.rep1, DL.n_rep1, b, z, em))) return rc;
+    } else {
+        if (!skip_repeat && (rc = colour_update<T>(pb, l, 1, b, z))) return rc;
+        if ((rc = colour_update<T>(pb, l, 1, b, z, em))) return rc;
+    }
     return colour_update<T>(pb, l, 0, b, z, em);
 }
 
@@ -371,14 +485,8 @@ int cheb_smooth(sbm_problem *pb, int l, const T *b, T *z, bool from_zero) {
     for (int k = 0; k < pb->opt.cheb_degree; ++k) {
         const T *r = b;
         if (!(k == 0 && from_zero)) {
-            KCHK(launch_cellop<T>(D.d, D.p, OP_RESID, 0, D.n_act, z, D.r, b,
-                                  [&] {
-                                      CellArgs<T> a = cell_args(D, false);
-                                      a.batch_start = D.batch_start;
-                                      a.nbatch = D.nbatch;
-                                      return a;
-                                  }(),
-                                  D.kref, pb->stream));
+            int rc;
+            if ((rc = level_apply<T>(pb, l, OP_RESID, z, D.r, b))) return rc;
             r = D.r;
         }
         double alpha = 0.0, beta = 1.0 / theta;
@@ -426,6 +534,9 @@ int vcycle_rec(sbm_problem *pb, int l, const T *b, T *z, const double *b64, bool
     auto &D = devlevels<T>(pb)[l];
     if (emitted) *emitted = false;
     if (l > 0 && pb->opt.smoother == 1) return vcycle_cheb<T>(pb, l, b, z, b64);
+    // a pencil level keeps its values to itself (the pencil kernel does not
+    // embed into the finer level): the caller prolongs them separately
+    if (l > 0 && D.pencil && em != nullptr && (em->kind == EMIT_H || em->kind == EMIT_P)) em = nullptr;
     if (l == 0) {
         if constexpr (std::is_same<T, float>::value) {
             // a one-level hierarchy: the FP32 copy of the right-hand side first
@@ -482,8 +593,11 @@ int check_level(sbm_problem *pb, int &level) {
 }  // namespace
 
 template <typename T>
-int refresh_level(sbm_problem *pb, const HostLevel &L, DevLevel<T> &D) {
+int refresh_level(sbm_problem *pb, int l, DevLevel<T> &D) {
+    const HostLevel &L = pb->levels[l];
     const int nc = L.nc;
+    int rc;
+    if ((rc = clip_lists(pb, l, D, false))) return rc;
     if (L.n_surr) {
         std::vector<T> sh(L.shifts.size());
         for (size_t i = 0; i < sh.size(); ++i) sh[i] = (T)(L.shifts[i] / L.h);
@@ -551,6 +665,7 @@ int sbm_default_options(int dim, int p, sbm_options *o) {
     o->smoother = 0;
     o->cheb_degree = 3;
     o->cheb_range = 20.0;
+    o->pencil = 1;
     o->stab = 0.0;
     o->device = 0;
     o->stream = nullptr;
@@ -618,7 +733,7 @@ static int setup_body(const sbm_geometry *g, int n, int p, const sbm_options *o,
         (op.ext != 0 && op.ext != 1) || op.penalty_p < 0 || op.penalty_p > 3 || !(op.lambda_frac >= 0.0) ||
         op.lambda_frac > 1.0 || op.frac_m < 1 || op.frac_m > 64 || !(op.stab >= 0.0) || op.min_neighbours < 0 ||
         op.min_neighbours > 2 * g->dim || (op.smoother != 0 && op.smoother != 1) || op.cheb_degree < 1 ||
-        op.cheb_degree > 64 || !(op.cheb_range > 1.0)) {
+        op.cheb_degree > 64 || !(op.cheb_range > 1.0) || (op.pencil != 0 && op.pencil != 1)) {
         delete pb;
         return SBM_EINVAL;
     }
@@ -799,6 +914,23 @@ int sbm_level_info(const sbm_problem *pb, int level, int *n, int *p, int *n_acti
     if (n_active) *n_active = L.n_act;
     if (n_colour0) *n_colour0 = L.n_col0;
     if (n_surr) *n_surr = L.n_surr;
+    return SBM_OK;
+}
+
+int sbm_level_blocks(const sbm_problem *pb, int level, int *n_boundary, int *n_clipped, int *n_clipped_colour0) {
+    if (!pb) return SBM_EINVAL;
+    int nl = (int)pb->levels.size();
+    if (level == -1) level = nl - 1;
+    if (level < 0 || level >= nl) return SBM_EINVAL;
+    const HostLevel &L = pb->levels[level];
+    int c0 = 0;
+    for (int K = 0; K < L.n_col0; ++K) {
+        const int bi = L.bnd_of[K];
+        if (bi >= 0 && (size_t)bi < L.clipped.size() && L.clipped[bi]) ++c0;
+    }
+    if (n_boundary) *n_boundary = L.n_bnd;
+    if (n_clipped) *n_clipped = L.n_clipped;
+    if (n_clipped_colour0) *n_clipped_colour0 = c0;
     return SBM_OK;
 }
 
@@ -1005,8 +1137,8 @@ static int set_shifts_body(sbm_problem *pb, int level, const double *shifts, lon
     if (!pb->host_only) {
         HIPCHK(hipSetDevice(pb->opt.device));
         HIPCHK(hipStreamSynchronize(pb->stream));
-        if ((rc = refresh_level<double>(pb, L, pb->dev64[level])) ||
-            (rc = refresh_level<float>(pb, L, pb->dev32[level])))
+        if ((rc = refresh_level<double>(pb, level, pb->dev64[level])) ||
+            (rc = refresh_level<float>(pb, level, pb->dev32[level])))
             return rc;
         if (level == 0)
             HIPCHK(hipMemcpy(pb->coarse.Ainv64, Ainv.data(), Ainv.size() * sizeof(double), hipMemcpyHostToDevice));

@@ -38,6 +38,7 @@ class Options(C.Structure):
                 ("vcycle_fp32", C.c_int), ("allow_singular", C.c_int), ("fuse_transfers", C.c_int),
                 ("penalty_p", C.c_int), ("lambda_frac", C.c_double), ("frac_m", C.c_int), ("min_neighbours", C.c_int), ("stab", C.c_double),
                 ("smoother", C.c_int), ("cheb_degree", C.c_int), ("cheb_range", C.c_double),
+                ("pencil", C.c_int),
                 ("device", C.c_int),
                 ("stream", C.c_void_p)]
 
@@ -63,6 +64,7 @@ SIGNATURES = [
     ("sbm_layout_info", C.c_int, [_VP, C.POINTER(Layout)]),
     ("sbm_active_cells", C.c_int, [_VP, C.c_int, C.POINTER(C.c_int), C.c_longlong]),
     ("sbm_level_info", C.c_int, [_VP, C.c_int] + [C.POINTER(C.c_int)] * 5),
+    ("sbm_level_blocks", C.c_int, [_VP, C.c_int] + [C.POINTER(C.c_int)] * 3),
     ("sbm_shifts", C.c_int, [_VP, C.c_int, C.POINTER(C.c_double), C.c_longlong]),
     ("sbm_set_shifts", C.c_int, [_VP, C.c_int, C.POINTER(C.c_double), C.c_longlong]),
     ("sbm_rhs", C.c_int, [_VP, FIELD_FN, FIELD_FN, _VP, _VP]),

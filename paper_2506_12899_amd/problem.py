@@ -106,6 +106,11 @@ class Problem:
         N.check(N.lib().sbm_level_info(self._h, level, *[C.byref(v) for v in vals]), self._h)
         return dict(zip(("n", "p", "n_active", "n_colour0", "n_surrogate_faces"), [v.value for v in vals]))
 
+    def level_blocks(self, level=-1):
+        vals = [C.c_int() for _ in range(3)]
+        N.check(N.lib().sbm_level_blocks(self._h, level, *[C.byref(v) for v in vals]), self._h)
+        return dict(zip(("n_boundary", "n_clipped", "n_clipped_colour0"), [v.value for v in vals]))
+
     def active_cells(self, level=-1):
         info = self.level_info(level)
         out = np.zeros((info["n_active"], self.dim), dtype=np.int32)

@@ -96,7 +96,7 @@ def test_colour_updates_sampled(full, fp32):
     name, prob, pb, L = full
     pb.set_vcycle_fp32(fp32)
     rng = np.random.default_rng(12)
-    omega = mg.default_omega(prob.p)
+    omega = prob.opts.get("omega", mg.default_omega(prob.p))
     b = _round(rng.standard_normal(L.n_dofs), fp32)
     z = _round(rng.standard_normal(L.n_dofs), fp32)
     Z = z.reshape(L.n_act, L.N)
@@ -278,7 +278,7 @@ def test_learned_correction_full_size():
     V = rng.standard_normal((nb, N, 4)) * 0.01
     P = lambda a: np.ascontiguousarray(a).ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
     Nn.check(Nn.lib().sbm_set_learned_arrays(pb._h, P(w), P(U), P(V)), pb._h)
-    omega = mg.default_omega(prob.p)
+    omega = prob.opts.get("omega", mg.default_omega(prob.p))
     for fp32 in (0, 1):
         pb.set_vcycle_fp32(fp32)
         wr, Ur, Vr = (_round(a, fp32) for a in (w, U, V))
