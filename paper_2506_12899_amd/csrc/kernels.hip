@@ -446,19 +446,28 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
                         T xc = c == k ? T(s) : (c == t1 ? R.gq[q1] : R.gq[q2]);
                         lagrange_dev<T, N1>(R.x, R.bw, xc + dq[c], lv[c]);
                     }
-                    T acc = 0, face = 0;
-#pragma unroll(SHIFT_UNROLL)
-                    for (int jj = 0; jj < NC; ++jj) {
-                        int a0 = jj % N1, a1 = (jj / N1) % N1, a2 = D == 3 ? jj / (N1 * N1) : 0;
-                        T pv = lv[0][a0] * lv[1][a1];
-                        if (D == 3) pv *= lv[2][a2];
-                        acc += pv * su[lc][jj];
+                    // sum factorised: x first (contiguous nodes), then y, then z
+                    T acc = 0;
+#pragma unroll
+                    for (int a2 = 0; a2 < (D == 3 ? N1 : 1); ++a2) {
+                        T s2 = 0;
+#pragma unroll
+                        for (int a1 = 0; a1 < N1; ++a1) {
+                            T s1 = 0;
+#pragma unroll
+                            for (int a0 = 0; a0 < N1; ++a0) s1 += lv[0][a0] * su[lc][a0 + N1 * (a1 + N1 * a2)];
+                            s2 += lv[1][a1] * s1;
+                        }
+                        acc += (D == 3 ? lv[2][a2] : T(1)) * s2;
                     }
-#pragma unroll(SHIFT_UNROLL)
-                    for (int j = 0; j < NF; ++j) {
-                        int j1 = j % N1, j2 = D == 3 ? j / N1 : 0;
-                        T sv = R.S[q1][j1] * (D == 3 ? R.S[q2][j2] : T(1));
-                        face += sv * su[lc][compose<D, P>(k, layer, j)];
+                    T face = 0;
+#pragma unroll
+                    for (int j2 = 0; j2 < (D == 3 ? N1 : 1); ++j2) {
+                        T f1 = 0;
+#pragma unroll
+                        for (int j1 = 0; j1 < N1; ++j1)
+                            f1 += R.S[q1][j1] * su[lc][compose<D, P>(k, layer, j1 + N1 * j2)];
+                        face += (D == 3 ? R.S[q2][j2] : T(1)) * f1;
                     }
                     E = acc - face;
                 }
@@ -936,6 +945,7 @@ __device__ __forceinline__ void smooth_zero_dof(long long t, int split, const TB
         for (int j = 0; j < NC; ++j) bv[j] = (T)bc[j];
     }
     if (bcopy != nullptr) bcopy[t] = (T)b[t];
+    if (c0 && bi < 0 && a.skip_interior) return;   // the pencil kernel's cell
     T out = 0;
     if (c0) {
         const T *Bt = bi < 0 ? a.Bint_t : a.Bbnd_t + (size_t)bi * NC * NC;

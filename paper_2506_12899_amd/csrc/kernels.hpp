@@ -24,6 +24,9 @@ struct CellArgs {
     // Optional cell list: the launch treats the cells perm[0 .. ncells)
     // instead of a contiguous range or the batch table
     const int *perm;
+    // zero-start update (smooth_zero): nonzero = interior colour-0 cells are
+    // left to the pencil kernel (neither computed nor written)
+    int skip_interior;
 };
 
 // waves per block of the cell kernels for cells of nc DoFs (measured: two
@@ -79,6 +82,10 @@ bool pencil_supported(int d, int p);
 template <typename T>
 int launch_pencil(int d, int p, int op, int ncells, const int *cells, const T *x, T *y, const T *b,
                   const CellArgs<T> &a, const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e);
+// the zero-start colour-0 update z_K = omega B_int b_K on the listed interior cells
+template <typename T, typename TB>
+int launch_pencil_zero(int d, int p, int ncells, const int *cells, const TB *b, T *z, const T *Bint_t, T omega,
+                       hipStream_t st);
 
 template <typename T>
 int launch_cellop(int d, int p, int op, int cell0, int ncells, const T *x, T *y, const T *b, const CellArgs<T> &a,

@@ -82,6 +82,72 @@ __device__ __forceinline__ T row_entry(const T (&M)[MAXN1][MAXN1], int row, int 
     return v;
 }
 
+// The shared interior inverse B_int (given transposed, [j][i]) staged into
+// LDS by the whole block, laid out [j][q][c] so that a lane's N1 outputs
+// i = q + NP c sit next to each other; load() issues the loads, store()
+// writes them (the caller's first loads go out in between).  SBL = false:
+// nothing (the columns are read from memory).
+template <int P, typename T, bool SBL>
+struct InverseStager {
+    static constexpr int N1 = P + 1, NP = N1 * N1, NC = NP * N1, NT = 64 * PSh<P>::WAVES;
+    static constexpr int PER = SBL ? (NC * NC + NT - 1) / NT : 1;
+    T v[PER];
+    __device__ __forceinline__ void load(const T *__restrict__ Bint_t) {
+        if constexpr (SBL) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int t = (int)threadIdx.x + k * NT;   // destination index [j][qq][c]
+                const int j = t / NC, rem = t % NC, qq = rem / N1, c = rem % N1;
+                v[k] = t < NC * NC ? Bint_t[(size_t)j * NC + qq + NP * c] : T(0);
+            }
+        }
+    }
+    __device__ __forceinline__ void store(T *sB) const {
+        if constexpr (SBL) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int t = (int)threadIdx.x + k * NT;
+                if (t < NC * NC) sB[t] = v[k];
+            }
+        }
+    }
+};
+
+// corr[c] = (B_int r)_(q + NP c), c = 0..P: r is the cell's residual in LDS;
+// B_int from the staged copy (SBL) or its transposed columns in memory, read
+// in groups of JB loads in flight
+template <int P, typename T, bool SBL>
+__device__ __forceinline__ void interior_correction(const T *sB, const T *__restrict__ Bint_t, const T *r, int q,
+                                                    T (&corr)[P + 1]) {
+    constexpr int N1 = P + 1, NP = N1 * N1, NC = NP * N1;
+#pragma unroll
+    for (int c = 0; c < N1; ++c) corr[c] = 0;
+    if constexpr (SBL) {
+#pragma unroll 8
+        for (int j = 0; j < NC; ++j) {
+            const T rj = r[j];
+#pragma unroll
+            for (int c = 0; c < N1; ++c) corr[c] += sB[(j * NP + q) * N1 + c] * rj;
+        }
+    } else {
+        constexpr int JB = NC % 8 == 0 ? 8 : (NC % 9 == 0 ? 9 : 1);
+#pragma unroll 1
+        for (int j0 = 0; j0 < NC; j0 += JB) {
+            T col[JB][N1];
+#pragma unroll
+            for (int jj = 0; jj < JB; ++jj)
+#pragma unroll
+                for (int c = 0; c < N1; ++c) col[jj][c] = Bint_t[(size_t)(j0 + jj) * NC + q + NP * c];
+#pragma unroll
+            for (int jj = 0; jj < JB; ++jj) {
+                const T rj = r[j0 + jj];
+#pragma unroll
+                for (int c = 0; c < N1; ++c) corr[c] += col[jj][c] * rj;
+            }
+        }
+    }
+}
+
 // OP_APPLY: out = A x; OP_RESID: out = b - A x; OP_SMOOTH: x (= out) += omega
 // B_int (b - A x) on the listed cells (F64OUT: the new values also go to z64).
 // cells[0 .. ncells): interior cells of the level.
@@ -110,17 +176,8 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
     const bool live = inslot && pos < ncells;
 
     // ---- loads: the staged inverse, the cell's own data and its neighbour indices
-    constexpr int NT = 64 * S::WAVES;
-    constexpr int SPER = SBL ? (NC * NC + NT - 1) / NT : 1;
-    T sbv[SPER];
-    if constexpr (SBL) {
-#pragma unroll
-        for (int k = 0; k < SPER; ++k) {
-            const int t = (int)threadIdx.x + k * NT;   // destination index [j][qq][c]
-            const int j = t / NC, rem = t % NC, qq = rem / N1, c = rem % N1;
-            sbv[k] = t < NC * NC ? Bint_t[(size_t)j * NC + qq + NP * c] : T(0);
-        }
-    }
+    InverseStager<P, T, SBL> bst;
+    bst.load(Bint_t);
     const int cell = live ? cells[pos] : 0;
     const T *xc = xin + (size_t)cell * NC;
     T u[N1], bv[N1], xz[N1];
@@ -161,13 +218,7 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
             zl[s][m] = nz[qa + N1 * qb + NP * m];
         }
     }
-    if constexpr (SBL) {
-#pragma unroll
-        for (int k = 0; k < SPER; ++k) {
-            const int t = (int)threadIdx.x + k * NT;
-            if (t < NC * NC) sB[t] = sbv[k];
-        }
-    }
+    bst.store(sB);
 
     // ---- stage x: A = M u, B = T u + E_x f_x along x at (y, z) = (qa, qb)
     T A[N1], B[N1];
@@ -325,33 +376,7 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
         wave_sync();
         if constexpr (SBL) __syncthreads();   // the staged inverse
         T corr[N1];
-#pragma unroll
-        for (int c = 0; c < N1; ++c) corr[c] = 0;
-        if constexpr (SBL) {
-#pragma unroll 8
-            for (int j = 0; j < NC; ++j) {
-                const T r = L.v0[lc][j];
-#pragma unroll
-                for (int c = 0; c < N1; ++c) corr[c] += sB[(j * NP + q) * N1 + c] * r;
-            }
-        } else {
-            // columns of B_int^T in groups of JB loads in flight
-            constexpr int JB = NC % 8 == 0 ? 8 : (NC % 9 == 0 ? 9 : 1);
-#pragma unroll 1
-            for (int j0 = 0; j0 < NC; j0 += JB) {
-                T col[JB][N1];
-#pragma unroll
-                for (int jj = 0; jj < JB; ++jj)
-#pragma unroll
-                    for (int c = 0; c < N1; ++c) col[jj][c] = Bint_t[(size_t)(j0 + jj) * NC + q + NP * c];
-#pragma unroll
-                for (int jj = 0; jj < JB; ++jj) {
-                    const T r = L.v0[lc][j0 + jj];
-#pragma unroll
-                    for (int c = 0; c < N1; ++c) corr[c] += col[jj][c] * r;
-                }
-            }
-        }
+        interior_correction<P, T, SBL>(sB, Bint_t, L.v0[lc], q, corr);
         if (live) {
 #pragma unroll
             for (int c = 0; c < N1; ++c) {
@@ -360,6 +385,47 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
                 if constexpr (F64OUT) z64[(size_t)cell * NC + q + NP * c] = (double)xn;
             }
         }
+    }
+}
+
+// First colour-0 update from z = 0 on the listed interior cells: the residual
+// is b itself, z_K = omega B_int b_K (b read in its own precision TB).
+template <int P, typename T, typename TB>
+__global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int ncells, const int *__restrict__ cells,
+                                                                          const TB *__restrict__ b,
+                                                                          T *__restrict__ z,
+                                                                          const T *__restrict__ Bint_t, T omega) {
+    using S = PSh<P>;
+    constexpr int N1 = S::N1, NP = S::NP, NC = S::NC, CPW = S::CPW;
+    constexpr bool FULL = CPW * NP == 64;
+    constexpr bool SBL = sizeof(T) == 4;
+    __shared__ T sr[S::CPB][NC];
+    __shared__ T sB[SBL ? NC * NC : 1];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = lane / NP;
+    const bool inslot = FULL || slot < CPW;
+    const int q = inslot ? lane - slot * NP : 0;
+    const int lc = wave * CPW + (inslot ? slot : 0);
+    const int pos = xcd_remap(blockIdx.x, gridDim.x) * S::CPB + lc;
+    const bool live = inslot && pos < ncells;
+    InverseStager<P, T, SBL> bst;
+    bst.load(Bint_t);
+    const int cell = live ? cells[pos] : 0;
+    T bv[N1];
+#pragma unroll
+    for (int c = 0; c < N1; ++c) bv[c] = (T)b[(size_t)cell * NC + q + NP * c];
+    bst.store(sB);
+    if (inslot) {
+#pragma unroll
+        for (int c = 0; c < N1; ++c) sr[lc][q + NP * c] = bv[c];
+    }
+    wave_sync();
+    if constexpr (SBL) __syncthreads();
+    T corr[N1];
+    interior_correction<P, T, SBL>(sB, Bint_t, sr[lc], q, corr);
+    if (live) {
+#pragma unroll
+        for (int c = 0; c < N1; ++c) z[(size_t)cell * NC + q + NP * c] = T(0) + omega * corr[c];
     }
 }
 
@@ -409,5 +475,28 @@ template int launch_pencil<double>(int, int, int, int, const int *, const double
                                    const EmitArgs<double> *);
 template int launch_pencil<float>(int, int, int, int, const int *, const float *, float *, const float *,
                                   const CellArgs<float> &, const KRef<float> &, hipStream_t, const EmitArgs<float> *);
+
+template <typename T, typename TB>
+int launch_pencil_zero(int d, int p, int ncells, const int *cells, const TB *b, T *z, const T *Bint_t, T omega,
+                       hipStream_t st) {
+    if (ncells <= 0) return 0;
+    if (!pencil_supported(d, p) || cells == nullptr) return -1;
+    if (p == 3) {
+        using S = PSh<3>;
+        hipLaunchKernelGGL((pencil_zero_kernel<3, T, TB>), dim3((ncells + S::CPB - 1) / S::CPB), dim3(64 * S::WAVES), 0,
+                           st, ncells, cells, b, z, Bint_t, omega);
+    } else {
+        using S = PSh<2>;
+        hipLaunchKernelGGL((pencil_zero_kernel<2, T, TB>), dim3((ncells + S::CPB - 1) / S::CPB), dim3(64 * S::WAVES), 0,
+                           st, ncells, cells, b, z, Bint_t, omega);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template int launch_pencil_zero<double, double>(int, int, int, const int *, const double *, double *, const double *,
+                                                double, hipStream_t);
+template int launch_pencil_zero<float, float>(int, int, int, const int *, const float *, float *, const float *, float,
+                                              hipStream_t);
+template int launch_pencil_zero<float, double>(int, int, int, const int *, const double *, float *, const float *,
+                                               float, hipStream_t);
 
 }  // namespace sbm

@@ -269,6 +269,7 @@ CellArgs<T> cell_args(const DevLevel<T> &D, bool learned) {
     a.nbatch = 0;
     a.split = D.n_col0;
     a.perm = nullptr;
+    a.skip_interior = 0;
     return a;
 }
 
@@ -285,9 +286,10 @@ int level_apply(sbm_problem *pb, int l, int op, const T *x, T *y, const T *b) {
     CellArgs<T> a = cell_args(D, false);
     if (D.pencil) {
         // interior cells by the pencil kernel, boundary cells by the cell kernel
-        KCHK(launch_pencil<T>(D.d, D.p, op, D.n_int0 + D.n_int1, D.pen_all, x, y, b, a, D.kref, pb->stream, nullptr));
+        // (disjoint outputs)
         a.perm = D.bnd_list;
         KCHK(launch_cellop<T>(D.d, D.p, op, 0, D.n_bl0 + D.n_bl1, x, y, b, a, D.kref, pb->stream));
+        KCHK(launch_pencil<T>(D.d, D.p, op, D.n_int0 + D.n_int1, D.pen_all, x, y, b, a, D.kref, pb->stream, nullptr));
         return SBM_OK;
     }
     a.batch_start = D.batch_start;
@@ -304,13 +306,15 @@ int colour_update(sbm_problem *pb, int l, int colour, const T *b, T *z, const Em
     int nc = colour == 0 ? D.n_col0 : D.n_act - D.n_col0;
     bool learned = pb->learned_on && D.lw != nullptr && l == (int)pb->levels.size() - 1;
     if (D.pencil && (em == nullptr || em->kind == EMIT_F64)) {
-        // the learned correction acts on boundary cells only
+        // the learned correction acts on boundary cells only (the same inputs,
+        // disjoint outputs)
         CellArgs<T> a = cell_args(D, learned);
+        a.perm = D.bnd_list + (colour == 0 ? 0 : D.n_bl0);
+        KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, 0, colour == 0 ? D.n_bl0 : D.n_bl1, z, z, b, a, D.kref, pb->stream,
+                              em));
+        a.perm = nullptr;
         KCHK(launch_pencil<T>(D.d, D.p, OP_SMOOTH, colour == 0 ? D.n_int0 : D.n_int1,
                               D.pen_col + (colour == 0 ? 0 : D.n_int0), z, z, b, a, D.kref, pb->stream, em));
-        a.perm = D.bnd_list + (colour == 0 ? 0 : D.n_bl0);
-        KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, 0, colour == 0 ? D.n_bl0 : D.n_bl1, z, z, b, a, D.kref,
-                              pb->stream, em));
         return SBM_OK;
     }
     KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, c0, nc, z, z, b, cell_args(D, learned), D.kref, pb->stream, em));
@@ -433,6 +437,22 @@ int ssor_step(sbm_problem *pb, int l, const T *b, T *z, bool from_zero = false, 
     int rc;
     if (started) {
         // nothing: z holds the zero-start colour-0 update
+    } else if (from_zero && DL.pencil) {
+        // boundary cells, the colour-1 zeros and the FP32 copy of b by the
+        // per-DoF kernel, interior colour-0 cells by the pencil kernel
+        CellArgs<T> ca = cell_args(DL, learned_here && DL.lw != nullptr);
+        ca.skip_interior = 1;
+        const hipStream_t bs = pb->stream;   // (both launches on the problem's stream)
+        if (b64 != nullptr) {
+            KCHK((launch_smooth_zero<T, double>(DL.d, DL.p, DL.n_act, DL.n_col0, b64, const_cast<T *>(b), z, ca,
+                                                DL.kref.omega, bs)));
+            KCHK((launch_pencil_zero<T, double>(DL.d, DL.p, DL.n_int0, DL.pen_col, b64, z, DL.Bint_t, DL.kref.omega,
+                                                pb->stream)));
+        } else {
+            KCHK((launch_smooth_zero<T, T>(DL.d, DL.p, DL.n_act, DL.n_col0, b, (T *)nullptr, z, ca, DL.kref.omega, bs)));
+            KCHK((launch_pencil_zero<T, T>(DL.d, DL.p, DL.n_int0, DL.pen_col, b, z, DL.Bint_t, DL.kref.omega,
+                                           pb->stream)));
+        }
     } else if (from_zero) {
         auto &D = devlevels<T>(pb)[l];
         const CellArgs<T> ca = cell_args(D, learned_here && D.lw != nullptr);
