@@ -137,6 +137,7 @@ struct DevLevel {
     // boundary cells by colour (n_bl0 of colour 0 first) for the other kernel
     bool pencil = false;
     int *pen_all = nullptr, *pen_col = nullptr, *bnd_list = nullptr;
+    int *bl_cbnd = nullptr;   // p-transfer below: the next coarser level's block index of bnd_list's cells
     int n_int0 = 0, n_int1 = 0, n_bl0 = 0, n_bl1 = 0;
     // level work vectors (coarser levels and the FP32 cycle)
     T *z = nullptr, *b = nullptr, *r = nullptr;

@@ -82,6 +82,11 @@ bool pencil_supported(int d, int p);
 template <typename T>
 int launch_pencil(int d, int p, int op, int ncells, const int *cells, const T *x, T *y, const T *b,
                   const CellArgs<T> &a, const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e);
+// residual restricted to the same cells one degree down, bc = E^T (b - A x),
+// and zc = 0 there (when given), on the listed interior cells
+template <typename T>
+int launch_pencil_rr(int d, int p, int ncells, const int *cells, const T *x, const T *b, T *bc, T *zc,
+                     const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr, hipStream_t st);
 // the zero-start colour-0 update z_K = omega B_int b_K on the listed interior cells
 template <typename T, typename TB>
 int launch_pencil_zero(int d, int p, int ncells, const int *cells, const TB *b, T *z, const T *Bint_t, T omega,

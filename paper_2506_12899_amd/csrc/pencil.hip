@@ -149,14 +149,18 @@ __device__ __forceinline__ void interior_correction(const T *sB, const T *__rest
 }
 
 // OP_APPLY: out = A x; OP_RESID: out = b - A x; OP_SMOOTH: x (= out) += omega
-// B_int (b - A x) on the listed cells (F64OUT: the new values also go to z64).
-// cells[0 .. ncells): interior cells of the level.
+// B_int (b - A x) on the listed cells (F64OUT: the new values also go to z64);
+// OP_RESTRICT: bc = E^T (b - A x) on the same cell of the next coarser level,
+// degree P - 1 (Sec. 3.2 p-restriction, E = tr.P1[0] along each direction),
+// and zc = 0 there when zc is given (the coarser level's zero start on cells
+// of colour 1).  cells[0 .. ncells): interior cells of the level.
 template <int P, typename T, int OP, bool F64OUT>
 __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, const int *__restrict__ cells,
                                                                      const T *xin, T *out, const T *__restrict__ b,
                                                                      const int *__restrict__ nbr,
                                                                      const T *__restrict__ Bint_t, KRef<T> R,
-                                                                     double *__restrict__ z64) {
+                                                                     double *__restrict__ z64, T *__restrict__ bc,
+                                                                     T *__restrict__ zc, TransferArgs<T> tr) {
     using S = PSh<P>;
     constexpr int N1 = S::N1, NP = S::NP, NC = S::NC, CPW = S::CPW;
     constexpr bool FULL = CPW * NP == 64;
@@ -367,6 +371,60 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
 #pragma unroll
             for (int c = 0; c < N1; ++c) oc[q + NP * c] = bv[c] - y[c];
         }
+    } else if constexpr (OP == OP_RESTRICT) {
+        // the residual contracted with E along z, then y, then x; the coarse
+        // cell has N1C = P nodes per direction
+        constexpr int N1C = P, NCC = N1C * N1C * N1C;
+        T rz[N1C];
+#pragma unroll
+        for (int b2 = 0; b2 < N1C; ++b2) {
+            T acc = 0;
+#pragma unroll
+            for (int a = 0; a < N1; ++a) acc += tr.P1[0][a][b2] * (bv[a] - y[a]);
+            rz[b2] = acc;
+        }
+        wave_sync();   // the z stage has read v0 and v1
+        if (inslot) {
+#pragma unroll
+            for (int b2 = 0; b2 < N1C; ++b2) L.v0[lc][q + NP * b2] = rz[b2];   // [x][y][z coarse]
+        }
+        wave_sync();
+        // along y: lane q < N1 N1C takes fine x = q % N1, coarse z = q / N1
+        const bool ylane = q < N1 * N1C;
+        const int xa = q % N1, zb = ylane ? q / N1 : 0;
+        T ry[N1C];
+#pragma unroll
+        for (int b1 = 0; b1 < N1C; ++b1) {
+            T acc = 0;
+#pragma unroll
+            for (int a = 0; a < N1; ++a) acc += tr.P1[0][a][b1] * L.v0[lc][xa + N1 * a + NP * zb];
+            ry[b1] = acc;
+        }
+        if (inslot && ylane) {
+#pragma unroll
+            for (int b1 = 0; b1 < N1C; ++b1) L.v1[lc][xa + N1 * b1 + N1 * N1C * zb] = ry[b1];   // [x][y c][z c]
+        }
+        wave_sync();
+        // along x: lane q < N1C^2 takes coarse (y, z) = (q % N1C, q / N1C)
+        const bool xlane = q < N1C * N1C;
+        const int yb = q % N1C, zb2 = xlane ? q / N1C : 0;
+        T rx[N1C];
+#pragma unroll
+        for (int b0 = 0; b0 < N1C; ++b0) {
+            T acc = 0;
+#pragma unroll
+            for (int a = 0; a < N1; ++a) acc += tr.P1[0][a][b0] * L.v1[lc][a + N1 * yb + N1 * N1C * zb2];
+            rx[b0] = acc;
+        }
+        if (live && xlane) {
+            const size_t o = (size_t)cell * NCC + N1C * (yb + N1C * zb2);
+#pragma unroll
+            for (int b0 = 0; b0 < N1C; ++b0) bc[o + b0] = rx[b0];
+            if (zc != nullptr) {
+#pragma unroll
+                for (int b0 = 0; b0 < N1C; ++b0) zc[o + b0] = T(0);
+            }
+        }
     } else {
         wave_sync();   // the z stage has read v0
         if (inslot) {
@@ -436,17 +494,17 @@ static int launch_p(int op, int ncells, const int *cells, const T *x, T *y, cons
     const dim3 g((ncells + S::CPB - 1) / S::CPB), bl(64 * S::WAVES);
     if (op == OP_APPLY)
         hipLaunchKernelGGL((pencil_kernel<P, T, OP_APPLY, false>), g, bl, 0, st, ncells, cells, x, y, b, a.nbr,
-                           a.Bint_t, R, nullptr);
+                           a.Bint_t, R, nullptr, nullptr, nullptr, TransferArgs<T>{});
     else if (op == OP_RESID)
         hipLaunchKernelGGL((pencil_kernel<P, T, OP_RESID, false>), g, bl, 0, st, ncells, cells, x, y, b, a.nbr,
-                           a.Bint_t, R, nullptr);
+                           a.Bint_t, R, nullptr, nullptr, nullptr, TransferArgs<T>{});
     else if (op == OP_SMOOTH && z64 == nullptr)
         hipLaunchKernelGGL((pencil_kernel<P, T, OP_SMOOTH, false>), g, bl, 0, st, ncells, cells, x, y, b, a.nbr,
-                           a.Bint_t, R, nullptr);
+                           a.Bint_t, R, nullptr, nullptr, nullptr, TransferArgs<T>{});
     else if (op == OP_SMOOTH) {
         if constexpr (std::is_same<T, float>::value)
             hipLaunchKernelGGL((pencil_kernel<P, T, OP_SMOOTH, true>), g, bl, 0, st, ncells, cells, x, y, b, a.nbr,
-                               a.Bint_t, R, z64);
+                               a.Bint_t, R, z64, nullptr, nullptr, TransferArgs<T>{});
         else
             return -1;
     } else {
@@ -498,5 +556,30 @@ template int launch_pencil_zero<float, float>(int, int, int, const int *, const 
                                               hipStream_t);
 template int launch_pencil_zero<float, double>(int, int, int, const int *, const double *, float *, const float *,
                                                float, hipStream_t);
+
+template <typename T>
+int launch_pencil_rr(int d, int p, int ncells, const int *cells, const T *x, const T *b, T *bc, T *zc,
+                     const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr, hipStream_t st) {
+    if (ncells <= 0) return 0;
+    if (!pencil_supported(d, p) || cells == nullptr || bc == nullptr) return -1;
+    if (p == 3) {
+        using S = PSh<3>;
+        hipLaunchKernelGGL((pencil_kernel<3, T, OP_RESTRICT, false>), dim3((ncells + S::CPB - 1) / S::CPB),
+                           dim3(64 * S::WAVES), 0, st, ncells, cells, x, (T *)nullptr, b, a.nbr, a.Bint_t, R,
+                           (double *)nullptr, bc, zc, tr);
+    } else {
+        using S = PSh<2>;
+        hipLaunchKernelGGL((pencil_kernel<2, T, OP_RESTRICT, false>), dim3((ncells + S::CPB - 1) / S::CPB),
+                           dim3(64 * S::WAVES), 0, st, ncells, cells, x, (T *)nullptr, b, a.nbr, a.Bint_t, R,
+                           (double *)nullptr, bc, zc, tr);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template int launch_pencil_rr<double>(int, int, int, const int *, const double *, const double *, double *, double *,
+                                      const CellArgs<double> &, const KRef<double> &, const TransferArgs<double> &,
+                                      hipStream_t);
+template int launch_pencil_rr<float>(int, int, int, const int *, const float *, const float *, float *, float *,
+                                     const CellArgs<float> &, const KRef<float> &, const TransferArgs<float> &,
+                                     hipStream_t);
 
 }  // namespace sbm

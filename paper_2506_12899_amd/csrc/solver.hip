@@ -170,6 +170,11 @@ int upload_level(sbm_problem *pb, int l, DevLevel<T> &D) {
         if ((rc = upload(pb, &D.pen_all, all.data(), all.size())) || (rc = upload(pb, &D.pen_col, col.data(), col.size())) ||
             (rc = upload(pb, &D.bnd_list, bl.data(), bl.size())))
             return rc;
+        if (l > 0 && L.ratio == 1) {
+            std::vector<int> cb(bl.size());
+            for (size_t t = 0; t < bl.size(); ++t) cb[t] = pb->levels[l - 1].bnd_of[bl[t]];
+            if ((rc = upload(pb, &D.bl_cbnd, cb.data(), cb.size()))) return rc;
+        }
         D.pencil = true;
     }
     {
@@ -390,9 +395,25 @@ int resid_restrict(sbm_problem *pb, int l, const T *z, const T *b, T *bc, T *zc 
     const bool c1_only = nch == 1 && pb->opt.smoother == 0 && pb->opt.nu_pre > 0 && pb->opt.omega == 1.0 &&
                          pb->opt.allow_singular == 0 && !learned_here &&
                          (pb->levels[l].n_clipped == 0 || Df.hold != nullptr);
-    KCHK(launch_resid_restrict<T>(Df.d, Df.p, Dc.n_act, nch, Dc.p + 1, nch == 1 ? nullptr : Df.rr_perm,
-                                  nch == 1 ? nullptr : Df.rr_grp, z, b, bc, ca, Df.kref, tr, pb->stream,
-                                  zc != nullptr ? &zs : nullptr, c1_only));
+    if (c1_only && Df.pencil) {
+        // colour 0 of bc (and of the zero start) is zero; colour 1: boundary
+        // cells by the cell kernel on its list, interior cells by the pencil kernel
+        const long long n0 = (long long)Dc.n_col0 * Dc.nc;
+        KCHK(launch_fill<T>(n0, bc, T(0), pb->stream));
+        if (zc != nullptr) KCHK(launch_fill<T>(n0, zc, T(0), pb->stream));
+        ZeroStartArgs<T> zb = zs;
+        zb.grp_bnd = Df.bl_cbnd != nullptr ? Df.bl_cbnd + Df.n_bl0 : nullptr;
+        if (Df.n_bl1 > 0)
+            KCHK(launch_resid_restrict<T>(Df.d, Df.p, Df.n_bl1, 1, Dc.p + 1, Df.bnd_list + Df.n_bl0,
+                                          Df.bnd_list + Df.n_bl0, z, b, bc, ca, Df.kref, tr, pb->stream,
+                                          zc != nullptr ? &zb : nullptr, false));
+        KCHK(launch_pencil_rr<T>(Df.d, Df.p, Df.n_int1, Df.pen_col + Df.n_int0, z, b, bc, zc, ca, Df.kref, tr,
+                                 pb->stream));
+    } else {
+        KCHK(launch_resid_restrict<T>(Df.d, Df.p, Dc.n_act, nch, Dc.p + 1, nch == 1 ? nullptr : Df.rr_perm,
+                                      nch == 1 ? nullptr : Df.rr_grp, z, b, bc, ca, Df.kref, tr, pb->stream,
+                                      zc != nullptr ? &zs : nullptr, c1_only));
+    }
     if (c1_only && Df.n_clip0 > 0) {
         ZeroStartArgs<T> zl = zs;
         zl.grp_bnd = Df.clip0_cbnd;
