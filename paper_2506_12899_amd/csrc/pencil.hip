@@ -38,13 +38,30 @@ struct PSh {
     static constexpr int CPB = CPW * WAVES;  // cells per block
 };
 
+// Position of DoF i of cell slot lc in a stage array: for Q3 each line of 4
+// nodes along x is followed by one unused element and a cell takes 80 (the
+// line stride 5 and the cell stride, 16 banks apart, spread the x-, y- and
+// z-pencil accesses of a wave over the 32 LDS banks: a bank model of the four
+// access patterns gives 1.4x the conflict-free pass count against 3.2x
+// unpadded); the 27-DoF cells of Q2 are spread by their odd size already.
+template <int P>
+struct PLayout {
+    static constexpr int NC = PSh<P>::NC, NP = PSh<P>::NP;
+    static constexpr int VS = P == 3 ? 80 : NC;
+    // face arrays [side][va, vb][face node] of a cell: 64 values for Q3, stride
+    // 80 for the same reason
+    static constexpr int FS = P == 3 ? 80 : 4 * NP;
+    __device__ __forceinline__ static int at(int lc, int i) { return lc * VS + (P == 3 ? i + (i >> 2) : i); }
+    __device__ __forceinline__ static int face(int lc, int s, int w, int j) { return lc * FS + (2 * s + w) * NP + j; }
+};
+
 template <int P, typename T>
 struct PencilLds {
-    static constexpr int CPB = PSh<P>::CPB, NC = PSh<P>::NC, NP = PSh<P>::NP;
-    T v0[CPB][NC];         // A, then Q, then (smoother) the residual
-    T v1[CPB][NC];         // B, then R
-    T fa[CPB][2][2][NP];   // face data [side][va, vb][face node]
-    T fg[CPB][2][2][NP];   // z-face data after the x contraction
+    static constexpr int CPB = PSh<P>::CPB, VS = PLayout<P>::VS, FS = PLayout<P>::FS;
+    T v0[CPB * VS];   // A, then Q, then (smoother) the residual
+    T v1[CPB * VS];   // B, then R
+    T fa[CPB * FS];   // face data
+    T fg[CPB * FS];   // z-face data after the x contraction
 };
 
 // face data of one neighbour line (its nodes along the face normal, from the
@@ -113,7 +130,8 @@ struct InverseStager {
     }
 };
 
-// corr[c] = (B_int r)_(q + NP c), c = 0..P: r is the cell's residual in LDS;
+// corr[c] = (B_int r)_(q + NP c), c = 0..P: r is the cell's residual in LDS
+// (stage-array layout, PLayout);
 // B_int from the staged copy (SBL) or its transposed columns in memory, read
 // in groups of JB loads in flight
 template <int P, typename T, bool SBL>
@@ -125,7 +143,7 @@ __device__ __forceinline__ void interior_correction(const T *sB, const T *__rest
     if constexpr (SBL) {
 #pragma unroll 8
         for (int j = 0; j < NC; ++j) {
-            const T rj = r[j];
+            const T rj = r[PLayout<P>::at(0, j)];
 #pragma unroll
             for (int c = 0; c < N1; ++c) corr[c] += sB[(j * NP + q) * N1 + c] * rj;
         }
@@ -140,7 +158,7 @@ __device__ __forceinline__ void interior_correction(const T *sB, const T *__rest
                 for (int c = 0; c < N1; ++c) col[jj][c] = Bint_t[(size_t)(j0 + jj) * NC + q + NP * c];
 #pragma unroll
             for (int jj = 0; jj < JB; ++jj) {
-                const T rj = r[j0 + jj];
+                const T rj = r[PLayout<P>::at(0, j0 + jj)];
 #pragma unroll
                 for (int c = 0; c < N1; ++c) corr[c] += col[jj][c] * rj;
             }
@@ -246,15 +264,15 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
     if (inslot) {
 #pragma unroll
         for (int c = 0; c < N1; ++c) {
-            L.v0[lc][c + N1 * q] = A[c];
-            L.v1[lc][c + N1 * q] = B[c];
+            L.v0[PLayout<P>::at(lc, c + N1 * q)] = A[c];
+            L.v1[PLayout<P>::at(lc, c + N1 * q)] = B[c];
         }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             T va, vb;
             face_data<P>(R, s, yl[s], va, vb);
-            L.fa[lc][s][0][q] = va;
-            L.fa[lc][s][1][q] = vb;
+            L.fa[PLayout<P>::face(lc, s, 0, q)] = va;
+            L.fa[PLayout<P>::face(lc, s, 1, q)] = vb;
         }
     }
     wave_sync();
@@ -265,8 +283,8 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
         T a[N1], bb[N1];
 #pragma unroll
         for (int m = 0; m < N1; ++m) {
-            a[m] = L.v0[lc][qa + N1 * m + NP * qb];
-            bb[m] = L.v1[lc][qa + N1 * m + NP * qb];
+            a[m] = L.v0[PLayout<P>::at(lc, qa + N1 * m + NP * qb)];
+            bb[m] = L.v1[PLayout<P>::at(lc, qa + N1 * m + NP * qb)];
         }
 #pragma unroll
         for (int c = 0; c < N1; ++c) {
@@ -285,8 +303,8 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
             T fa = 0, fb = 0;
 #pragma unroll
             for (int m = 0; m < N1; ++m) {
-                fa += Ma[m] * L.fa[lc][s][0][m + N1 * qb];
-                fb += Ma[m] * L.fa[lc][s][1][m + N1 * qb];
+                fa += Ma[m] * L.fa[PLayout<P>::face(lc, s, 0, m + N1 * qb)];
+                fb += Ma[m] * L.fa[PLayout<P>::face(lc, s, 1, m + N1 * qb)];
             }
             inject<P>(R, s, fa, fb, Rv);
         }
@@ -295,15 +313,15 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
     if (inslot) {
 #pragma unroll
         for (int c = 0; c < N1; ++c) {
-            L.v0[lc][qa + N1 * c + NP * qb] = Qv[c];
-            L.v1[lc][qa + N1 * c + NP * qb] = Rv[c];
+            L.v0[PLayout<P>::at(lc, qa + N1 * c + NP * qb)] = Qv[c];
+            L.v1[PLayout<P>::at(lc, qa + N1 * c + NP * qb)] = Rv[c];
         }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             T va, vb;
             face_data<P>(R, s, zl[s], va, vb);
-            L.fa[lc][s][0][q] = va;
-            L.fa[lc][s][1][q] = vb;
+            L.fa[PLayout<P>::face(lc, s, 0, q)] = va;
+            L.fa[PLayout<P>::face(lc, s, 1, q)] = vb;
         }
     }
     wave_sync();
@@ -316,14 +334,14 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
             for (int w = 0; w < 2; ++w) {
                 T acc = 0;
 #pragma unroll
-                for (int m = 0; m < N1; ++m) acc += Ma[m] * L.fa[lc][s][w][m + N1 * qb];
+                for (int m = 0; m < N1; ++m) acc += Ma[m] * L.fa[PLayout<P>::face(lc, s, w, m + N1 * qb)];
                 g[s][w] = acc;
             }
         if (inslot) {
 #pragma unroll
             for (int s = 0; s < 2; ++s)
 #pragma unroll
-                for (int w = 0; w < 2; ++w) L.fg[lc][s][w][q] = g[s][w];
+                for (int w = 0; w < 2; ++w) L.fg[PLayout<P>::face(lc, s, w, q)] = g[s][w];
         }
     }
     wave_sync();
@@ -334,8 +352,8 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
         T qv[N1], rv[N1];
 #pragma unroll
         for (int m = 0; m < N1; ++m) {
-            qv[m] = L.v0[lc][q + NP * m];
-            rv[m] = L.v1[lc][q + NP * m];
+            qv[m] = L.v0[PLayout<P>::at(lc, q + NP * m)];
+            rv[m] = L.v1[PLayout<P>::at(lc, q + NP * m)];
         }
 #pragma unroll
         for (int c = 0; c < N1; ++c) {
@@ -350,8 +368,8 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
             T fa = 0, fb = 0;
 #pragma unroll
             for (int m = 0; m < N1; ++m) {
-                fa += Mb[m] * L.fg[lc][s][0][qa + N1 * m];
-                fb += Mb[m] * L.fg[lc][s][1][qa + N1 * m];
+                fa += Mb[m] * L.fg[PLayout<P>::face(lc, s, 0, qa + N1 * m)];
+                fb += Mb[m] * L.fg[PLayout<P>::face(lc, s, 1, qa + N1 * m)];
             }
             inject<P>(R, s, fa, fb, y);
         }
@@ -386,7 +404,7 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
         wave_sync();   // the z stage has read v0 and v1
         if (inslot) {
 #pragma unroll
-            for (int b2 = 0; b2 < N1C; ++b2) L.v0[lc][q + NP * b2] = rz[b2];   // [x][y][z coarse]
+            for (int b2 = 0; b2 < N1C; ++b2) L.v0[PLayout<P>::at(lc, q + NP * b2)] = rz[b2];   // [x][y][z coarse]
         }
         wave_sync();
         // along y: lane q < N1 N1C takes fine x = q % N1, coarse z = q / N1
@@ -397,12 +415,12 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
         for (int b1 = 0; b1 < N1C; ++b1) {
             T acc = 0;
 #pragma unroll
-            for (int a = 0; a < N1; ++a) acc += tr.P1[0][a][b1] * L.v0[lc][xa + N1 * a + NP * zb];
+            for (int a = 0; a < N1; ++a) acc += tr.P1[0][a][b1] * L.v0[PLayout<P>::at(lc, xa + N1 * a + NP * zb)];
             ry[b1] = acc;
         }
         if (inslot && ylane) {
 #pragma unroll
-            for (int b1 = 0; b1 < N1C; ++b1) L.v1[lc][xa + N1 * b1 + N1 * N1C * zb] = ry[b1];   // [x][y c][z c]
+            for (int b1 = 0; b1 < N1C; ++b1) L.v1[PLayout<P>::at(lc, xa + N1 * b1 + N1 * N1C * zb)] = ry[b1];   // [x][y c][z c]
         }
         wave_sync();
         // along x: lane q < N1C^2 takes coarse (y, z) = (q % N1C, q / N1C)
@@ -413,7 +431,7 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
         for (int b0 = 0; b0 < N1C; ++b0) {
             T acc = 0;
 #pragma unroll
-            for (int a = 0; a < N1; ++a) acc += tr.P1[0][a][b0] * L.v1[lc][a + N1 * yb + N1 * N1C * zb2];
+            for (int a = 0; a < N1; ++a) acc += tr.P1[0][a][b0] * L.v1[PLayout<P>::at(lc, a + N1 * yb + N1 * N1C * zb2)];
             rx[b0] = acc;
         }
         if (live && xlane) {
@@ -429,12 +447,12 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
         wave_sync();   // the z stage has read v0
         if (inslot) {
 #pragma unroll
-            for (int c = 0; c < N1; ++c) L.v0[lc][q + NP * c] = bv[c] - y[c];
+            for (int c = 0; c < N1; ++c) L.v0[PLayout<P>::at(lc, q + NP * c)] = bv[c] - y[c];
         }
         wave_sync();
         if constexpr (SBL) __syncthreads();   // the staged inverse
         T corr[N1];
-        interior_correction<P, T, SBL>(sB, Bint_t, L.v0[lc], q, corr);
+        interior_correction<P, T, SBL>(sB, Bint_t, L.v0 + PLayout<P>::at(lc, 0), q, corr);
         if (live) {
 #pragma unroll
             for (int c = 0; c < N1; ++c) {
@@ -457,7 +475,7 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
     constexpr int N1 = S::N1, NP = S::NP, NC = S::NC, CPW = S::CPW;
     constexpr bool FULL = CPW * NP == 64;
     constexpr bool SBL = sizeof(T) == 4;
-    __shared__ T sr[S::CPB][NC];
+    __shared__ T sr[S::CPB * PLayout<P>::VS];
     __shared__ T sB[SBL ? NC * NC : 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = lane / NP;
@@ -475,12 +493,12 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
     bst.store(sB);
     if (inslot) {
 #pragma unroll
-        for (int c = 0; c < N1; ++c) sr[lc][q + NP * c] = bv[c];
+        for (int c = 0; c < N1; ++c) sr[PLayout<P>::at(lc, q + NP * c)] = bv[c];
     }
     wave_sync();
     if constexpr (SBL) __syncthreads();
     T corr[N1];
-    interior_correction<P, T, SBL>(sB, Bint_t, sr[lc], q, corr);
+    interior_correction<P, T, SBL>(sB, Bint_t, sr + PLayout<P>::at(lc, 0), q, corr);
     if (live) {
 #pragma unroll
         for (int c = 0; c < N1; ++c) z[(size_t)cell * NC + q + NP * c] = T(0) + omega * corr[c];
