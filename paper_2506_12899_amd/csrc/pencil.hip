@@ -185,9 +185,15 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
     // the smoother's shared inverse in LDS, laid out [j][q][c] (the lane's N1
     // outputs q + NP c next to each other); FP32 only (FP64: 32 KB per block
     // would halve the occupancy, its columns come from memory)
-    constexpr bool SBL = OP == OP_SMOOTH && sizeof(T) == 4;
+    // FP32 Q3: the block's 16 corrections B_int r_K as one 64 x 64 by 64 x 16
+    // product on the matrix cores (v_mfma_f32_16x16x4f32; wave w forms rows
+    // 16 w .. 16 w + 15 of all 16 cells, its slab of B_int held in registers);
+    // other FP32 levels: the VALU product with the inverse staged in LDS
+    constexpr bool MF = OP == OP_SMOOTH && sizeof(T) == 4 && P == 3;
+    constexpr bool SBL = OP == OP_SMOOTH && sizeof(T) == 4 && !MF;
     __shared__ PencilLds<P, T> L;
     __shared__ T sB[SBL ? NC * NC : 1];
+    __shared__ int scell[MF ? S::CPB : 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = lane / NP;
     const bool inslot = FULL || slot < CPW;
@@ -200,6 +206,14 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
     // ---- loads: the staged inverse, the cell's own data and its neighbour indices
     InverseStager<P, T, SBL> bst;
     bst.load(Bint_t);
+    // MF: this lane's entries of the wave's slab, A[i][k] = B_int[16 w + lane % 16][4 s + lane / 16]
+    // for the K steps s (operand layout of the 16x16x4 product: A[i][k] from lane i + 16 k)
+    constexpr int KS = MF ? NC / 4 : 1;
+    T bsl[KS];
+    if constexpr (MF) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bsl[ks] = Bint_t[(size_t)(4 * ks + lane / 16) * NC + 16 * wave + lane % 16];
+    }
     const int cell = live ? cells[pos] : 0;
     const T *xc = xin + (size_t)cell * NC;
     T u[N1], bv[N1], xz[N1];
@@ -209,9 +223,12 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
 #pragma unroll
         for (int c = 0; c < N1; ++c) bv[c] = b[(size_t)cell * NC + q + NP * c];
     }
-    if constexpr (OP == OP_SMOOTH) {
+    if constexpr (OP == OP_SMOOTH && !MF) {
 #pragma unroll
         for (int c = 0; c < N1; ++c) xz[c] = xc[q + NP * c];
+    }
+    if constexpr (MF) {
+        if (q == 0) scell[lc] = live ? cell : -1;
     }
     int nb[6];
 #pragma unroll
@@ -448,6 +465,34 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
         if (inslot) {
 #pragma unroll
             for (int c = 0; c < N1; ++c) L.v0[PLayout<P>::at(lc, q + NP * c)] = bv[c] - y[c];
+        }
+        if constexpr (MF) {
+            // all 16 residuals of the block, then Z = B_int R: B operand R[k][j]
+            // (cell slot j = lane % 16, DoF k = 4 s + lane / 16) from lane j + 16 k;
+            // result D[i][j] in lane j + 16 (i / 4), register i % 4
+            __syncthreads();
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+            const int col = lane % 16;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(bsl[ks], L.v0[PLayout<P>::at(col, 4 * ks + lane / 16)], acc,
+                                                           0, 0, 0);
+            const int ccell = scell[col];
+            if (ccell >= 0) {
+                const int i0 = 16 * wave + 4 * (lane / 16);
+                T *oz = out + (size_t)ccell * NC + i0;
+                f4 old = *reinterpret_cast<const f4 *>(xin + (size_t)ccell * NC + i0);
+                f4 nw;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) nw[r] = old[r] + R.omega * acc[r];
+                *reinterpret_cast<f4 *>(oz) = nw;
+                if constexpr (F64OUT) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) z64[(size_t)ccell * NC + i0 + r] = (double)nw[r];
+                }
+            }
+            return;
         }
         wave_sync();
         if constexpr (SBL) __syncthreads();   // the staged inverse
