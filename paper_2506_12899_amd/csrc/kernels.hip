@@ -523,16 +523,18 @@ __device__ __forceinline__ void cell_batch(CellLds<D, P, T, NW> &L, const T *sB,
 #pragma unroll
                 for (int j = 0; j < (PRE_B ? NC : 1); ++j) corr += bcol[j] * sa[lc][j];
             } else {
-                // large blocks: the column in groups of 16 loads in flight (the
-                // last group is cut at NC)
+                // large blocks: the column in groups of G loads in flight (the
+                // last group is cut at NC); FP32 takes 32 (two round trips for
+                // a 64-DoF cell instead of four), FP64 16 (register budget)
+                constexpr int G = sizeof(T) == 4 ? 32 : 16;
                 const T *Bt = (NC > 27 && bi < 0) ? a.Bint_t : a.Bbnd_t + (size_t)bi * NC * NC;
 #pragma unroll 1
-                for (int j0 = 0; j0 < NC; j0 += 16) {
-                    T col[16];
+                for (int j0 = 0; j0 < NC; j0 += G) {
+                    T col[G];
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) col[j] = Bt[(size_t)min(j0 + j, NC - 1) * NC + i];   // (clamped)
+                    for (int j = 0; j < G; ++j) col[j] = Bt[(size_t)min(j0 + j, NC - 1) * NC + i];   // (clamped)
 #pragma unroll
-                    for (int j = 0; j < 16; ++j)
+                    for (int j = 0; j < G; ++j)
                         if (j0 + j < NC) corr += col[j] * sa[lc][j0 + j];
                 }
             }

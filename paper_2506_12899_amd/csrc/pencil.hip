@@ -519,9 +519,11 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
     using S = PSh<P>;
     constexpr int N1 = S::N1, NP = S::NP, NC = S::NC, CPW = S::CPW;
     constexpr bool FULL = CPW * NP == 64;
-    constexpr bool SBL = sizeof(T) == 4;
+    constexpr bool MF = sizeof(T) == 4 && P == 3;    // as in the colour update
+    constexpr bool SBL = sizeof(T) == 4 && !MF;
     __shared__ T sr[S::CPB * PLayout<P>::VS];
     __shared__ T sB[SBL ? NC * NC : 1];
+    __shared__ int scell[MF ? S::CPB : 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = lane / NP;
     const bool inslot = FULL || slot < CPW;
@@ -531,6 +533,12 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
     const bool live = inslot && pos < ncells;
     InverseStager<P, T, SBL> bst;
     bst.load(Bint_t);
+    constexpr int KS = MF ? NC / 4 : 1;
+    T bsl[KS];
+    if constexpr (MF) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bsl[ks] = Bint_t[(size_t)(4 * ks + lane / 16) * NC + 16 * wave + lane % 16];
+    }
     const int cell = live ? cells[pos] : 0;
     T bv[N1];
 #pragma unroll
@@ -539,6 +547,25 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
     if (inslot) {
 #pragma unroll
         for (int c = 0; c < N1; ++c) sr[PLayout<P>::at(lc, q + NP * c)] = bv[c];
+    }
+    if constexpr (MF) {
+        if (q == 0) scell[lc] = live ? cell : -1;
+        __syncthreads();
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int col = lane % 16;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(bsl[ks], sr[PLayout<P>::at(col, 4 * ks + lane / 16)], acc, 0, 0,
+                                                       0);
+        const int ccell = scell[col];
+        if (ccell >= 0) {
+            f4 nw;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) nw[r] = T(0) + omega * acc[r];
+            *reinterpret_cast<f4 *>(z + (size_t)ccell * NC + 16 * wave + 4 * (lane / 16)) = nw;
+        }
+        return;
     }
     wave_sync();
     if constexpr (SBL) __syncthreads();
