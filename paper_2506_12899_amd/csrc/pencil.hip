@@ -194,6 +194,11 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
     __shared__ PencilLds<P, T> L;
     __shared__ T sB[SBL ? NC * NC : 1];
     __shared__ int scell[MF ? S::CPB : 1];
+    // MF: the block's residuals as the product's B operand, [DoF][cell slot],
+    // rows of CPB + 1 (the writes of a cell's 16 lanes and the operand reads of
+    // a half-wave fall on distinct banks)
+    constexpr int RS = S::CPB + 1;
+    __shared__ T sRm[MF ? NC * RS : 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = lane / NP;
     const bool inslot = FULL || slot < CPW;
@@ -461,23 +466,19 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
             }
         }
     } else {
-        wave_sync();   // the z stage has read v0
-        if (inslot) {
-#pragma unroll
-            for (int c = 0; c < N1; ++c) L.v0[PLayout<P>::at(lc, q + NP * c)] = bv[c] - y[c];
-        }
         if constexpr (MF) {
             // all 16 residuals of the block, then Z = B_int R: B operand R[k][j]
             // (cell slot j = lane % 16, DoF k = 4 s + lane / 16) from lane j + 16 k;
             // result D[i][j] in lane j + 16 (i / 4), register i % 4
+#pragma unroll
+            for (int c = 0; c < N1; ++c) sRm[(q + NP * c) * RS + lc] = bv[c] - y[c];
             __syncthreads();
             typedef float f4 __attribute__((ext_vector_type(4)));
             f4 acc = {0.f, 0.f, 0.f, 0.f};
             const int col = lane % 16;
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(bsl[ks], L.v0[PLayout<P>::at(col, 4 * ks + lane / 16)], acc,
-                                                           0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(bsl[ks], sRm[(4 * ks + lane / 16) * RS + col], acc, 0, 0, 0);
             const int ccell = scell[col];
             if (ccell >= 0) {
                 const int i0 = 16 * wave + 4 * (lane / 16);
@@ -493,6 +494,11 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
                 }
             }
             return;
+        }
+        wave_sync();   // the z stage has read v0
+        if (inslot) {
+#pragma unroll
+            for (int c = 0; c < N1; ++c) L.v0[PLayout<P>::at(lc, q + NP * c)] = bv[c] - y[c];
         }
         wave_sync();
         if constexpr (SBL) __syncthreads();   // the staged inverse
@@ -521,9 +527,11 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
     constexpr bool FULL = CPW * NP == 64;
     constexpr bool MF = sizeof(T) == 4 && P == 3;    // as in the colour update
     constexpr bool SBL = sizeof(T) == 4 && !MF;
-    __shared__ T sr[S::CPB * PLayout<P>::VS];
+    __shared__ T sr[MF ? 1 : S::CPB * PLayout<P>::VS];
     __shared__ T sB[SBL ? NC * NC : 1];
     __shared__ int scell[MF ? S::CPB : 1];
+    constexpr int RS = S::CPB + 1;   // as in the colour update
+    __shared__ T sRm[MF ? NC * RS : 1];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = lane / NP;
     const bool inslot = FULL || slot < CPW;
@@ -544,11 +552,9 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
 #pragma unroll
     for (int c = 0; c < N1; ++c) bv[c] = (T)b[(size_t)cell * NC + q + NP * c];
     bst.store(sB);
-    if (inslot) {
-#pragma unroll
-        for (int c = 0; c < N1; ++c) sr[PLayout<P>::at(lc, q + NP * c)] = bv[c];
-    }
     if constexpr (MF) {
+#pragma unroll
+        for (int c = 0; c < N1; ++c) sRm[(q + NP * c) * RS + lc] = bv[c];
         if (q == 0) scell[lc] = live ? cell : -1;
         __syncthreads();
         typedef float f4 __attribute__((ext_vector_type(4)));
@@ -556,8 +562,7 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
         const int col = lane % 16;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(bsl[ks], sr[PLayout<P>::at(col, 4 * ks + lane / 16)], acc, 0, 0,
-                                                       0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(bsl[ks], sRm[(4 * ks + lane / 16) * RS + col], acc, 0, 0, 0);
         const int ccell = scell[col];
         if (ccell >= 0) {
             f4 nw;
@@ -566,6 +571,10 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
             *reinterpret_cast<f4 *>(z + (size_t)ccell * NC + 16 * wave + 4 * (lane / 16)) = nw;
         }
         return;
+    }
+    if (inslot) {
+#pragma unroll
+        for (int c = 0; c < N1; ++c) sr[PLayout<P>::at(lc, q + NP * c)] = bv[c];
     }
     wave_sync();
     if constexpr (SBL) __syncthreads();

@@ -158,15 +158,28 @@ int upload_level(sbm_problem *pb, int l, DevLevel<T> &D) {
         }
         D.n_int1 = (int)col.size() - D.n_int0;
         D.n_bl1 = (int)bl.size() - D.n_bl0;
-        // mesh (lexicographic) order for whole-level operations: a cell's
-        // neighbours, of the other colour, are then near it in the launch
-        all = col;
+        // mesh order in tiles of 8^d cells for whole-level operations (a cell's
+        // neighbours, of the other colour, are then near it in the launch, and
+        // the cells an XCD has in flight with their neighbours fit its L2),
+        // the same tile order inside each colour
         auto key = [&](int K) {
-            long long v = 0;
-            for (int c = L.d - 1; c >= 0; --c) v = v * L.n + L.cells[(size_t)K * L.d + c];
-            return v;
+            constexpr int TB = 8;
+            const int nt = (L.n + TB - 1) / TB;
+            long long tile = 0, in = 0;
+            for (int c = L.d - 1; c >= 0; --c) {
+                const int v = L.cells[(size_t)K * L.d + c];
+                tile = tile * nt + v / TB;
+                in = in * TB + v % TB;
+            }
+            long long cells_per_tile = 1;
+            for (int c = 0; c < L.d; ++c) cells_per_tile *= TB;
+            return tile * cells_per_tile + in;
         };
-        std::sort(all.begin(), all.end(), [&](int x, int y) { return key(x) < key(y); });
+        auto by_key = [&](int x, int y) { return key(x) < key(y); };
+        std::sort(col.begin(), col.begin() + D.n_int0, by_key);
+        std::sort(col.begin() + D.n_int0, col.end(), by_key);
+        all = col;
+        std::sort(all.begin(), all.end(), by_key);
         if ((rc = upload(pb, &D.pen_all, all.data(), all.size())) || (rc = upload(pb, &D.pen_col, col.data(), col.size())) ||
             (rc = upload(pb, &D.bnd_list, bl.data(), bl.size())))
             return rc;
