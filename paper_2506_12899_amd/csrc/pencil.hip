@@ -99,6 +99,30 @@ __device__ __forceinline__ T row_entry(const T (&M)[MAXN1][MAXN1], int row, int 
     return v;
 }
 
+// One K step of a 16 x 16 tile product on the matrix cores, D += A B with A
+// 16 x 4, B 4 x 16 (wave64 operand layout: A[i][k] from lane i + 16 k, B[k][j]
+// from lane j + 16 k; the result D[i][j] sits in lane j + 16 g, register r,
+// with i = row(g, r): 4 g + r in FP32, g + 4 r in FP64; both checked by an
+// in-bounds probe)
+template <typename T>
+struct Tile16;
+template <>
+struct Tile16<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __device__ __forceinline__ static v4 step(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static int row(int g, int r) { return 4 * g + r; }
+};
+template <>
+struct Tile16<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __device__ __forceinline__ static v4 step(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ __forceinline__ static int row(int g, int r) { return g + 4 * r; }
+};
+
 // The shared interior inverse B_int (given transposed, [j][i]) staged into
 // LDS by the whole block, laid out [j][q][c] so that a lane's N1 outputs
 // i = q + NP c sit next to each other; load() issues the loads, store()
@@ -185,11 +209,11 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
     // the smoother's shared inverse in LDS, laid out [j][q][c] (the lane's N1
     // outputs q + NP c next to each other); FP32 only (FP64: 32 KB per block
     // would halve the occupancy, its columns come from memory)
-    // FP32 Q3: the block's 16 corrections B_int r_K as one 64 x 64 by 64 x 16
-    // product on the matrix cores (v_mfma_f32_16x16x4f32; wave w forms rows
-    // 16 w .. 16 w + 15 of all 16 cells, its slab of B_int held in registers);
-    // other FP32 levels: the VALU product with the inverse staged in LDS
-    constexpr bool MF = OP == OP_SMOOTH && sizeof(T) == 4 && P == 3;
+    // Q3: the block's 16 corrections B_int r_K as one 64 x 64 by 64 x 16
+    // product on the matrix cores (16x16x4 tiles, FP32 or FP64; wave w forms
+    // rows 16 w .. 16 w + 15 of all 16 cells, its slab of B_int held in
+    // registers); Q2: the VALU product, FP32 with the inverse staged in LDS
+    constexpr bool MF = OP == OP_SMOOTH && P == 3;
     constexpr bool SBL = OP == OP_SMOOTH && sizeof(T) == 4 && !MF;
     __shared__ PencilLds<P, T> L;
     __shared__ T sB[SBL ? NC * NC : 1];
@@ -473,24 +497,32 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
 #pragma unroll
             for (int c = 0; c < N1; ++c) sRm[(q + NP * c) * RS + lc] = bv[c] - y[c];
             __syncthreads();
-            typedef float f4 __attribute__((ext_vector_type(4)));
-            f4 acc = {0.f, 0.f, 0.f, 0.f};
+            typedef typename Tile16<T>::v4 f4;
+            f4 acc = {T(0), T(0), T(0), T(0)};
             const int col = lane % 16;
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(bsl[ks], sRm[(4 * ks + lane / 16) * RS + col], acc, 0, 0, 0);
+            for (int ks = 0; ks < KS; ++ks) acc = Tile16<T>::step(bsl[ks], sRm[(4 * ks + lane / 16) * RS + col], acc);
             const int ccell = scell[col];
             if (ccell >= 0) {
-                const int i0 = 16 * wave + 4 * (lane / 16);
-                T *oz = out + (size_t)ccell * NC + i0;
-                f4 old = *reinterpret_cast<const f4 *>(xin + (size_t)ccell * NC + i0);
-                f4 nw;
+                const size_t o = (size_t)ccell * NC + 16 * wave;
+                const int g = lane / 16;
+                if constexpr (sizeof(T) == 4) {
+                    // rows 4 g .. 4 g + 3: one vector access
+                    f4 old = *reinterpret_cast<const f4 *>(xin + o + 4 * g);
+                    f4 nw;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) nw[r] = old[r] + R.omega * acc[r];
-                *reinterpret_cast<f4 *>(oz) = nw;
-                if constexpr (F64OUT) {
+                    for (int r = 0; r < 4; ++r) nw[r] = old[r] + R.omega * acc[r];
+                    *reinterpret_cast<f4 *>(out + o + 4 * g) = nw;
+                    if constexpr (F64OUT) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) z64[(size_t)ccell * NC + i0 + r] = (double)nw[r];
+                        for (int r = 0; r < 4; ++r) z64[o + 4 * g + r] = (double)nw[r];
+                    }
+                } else {
+                    T old[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) old[r] = xin[o + Tile16<T>::row(g, r)];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) out[o + Tile16<T>::row(g, r)] = old[r] + R.omega * acc[r];
                 }
             }
             return;
@@ -525,7 +557,7 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
     using S = PSh<P>;
     constexpr int N1 = S::N1, NP = S::NP, NC = S::NC, CPW = S::CPW;
     constexpr bool FULL = CPW * NP == 64;
-    constexpr bool MF = sizeof(T) == 4 && P == 3;    // as in the colour update
+    constexpr bool MF = P == 3;    // as in the colour update
     constexpr bool SBL = sizeof(T) == 4 && !MF;
     __shared__ T sr[MF ? 1 : S::CPB * PLayout<P>::VS];
     __shared__ T sB[SBL ? NC * NC : 1];
@@ -557,18 +589,16 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
         for (int c = 0; c < N1; ++c) sRm[(q + NP * c) * RS + lc] = bv[c];
         if (q == 0) scell[lc] = live ? cell : -1;
         __syncthreads();
-        typedef float f4 __attribute__((ext_vector_type(4)));
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        typedef typename Tile16<T>::v4 f4;
+        f4 acc = {T(0), T(0), T(0), T(0)};
         const int col = lane % 16;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(bsl[ks], sRm[(4 * ks + lane / 16) * RS + col], acc, 0, 0, 0);
+        for (int ks = 0; ks < KS; ++ks) acc = Tile16<T>::step(bsl[ks], sRm[(4 * ks + lane / 16) * RS + col], acc);
         const int ccell = scell[col];
         if (ccell >= 0) {
-            f4 nw;
+            const size_t o = (size_t)ccell * NC + 16 * wave;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) nw[r] = T(0) + omega * acc[r];
-            *reinterpret_cast<f4 *>(z + (size_t)ccell * NC + 16 * wave + 4 * (lane / 16)) = nw;
+            for (int r = 0; r < 4; ++r) z[o + Tile16<T>::row(lane / 16, r)] = T(0) + omega * acc[r];
         }
         return;
     }
