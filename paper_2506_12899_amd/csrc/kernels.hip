@@ -1371,13 +1371,15 @@ template <typename T, int NC>
 __global__ __launch_bounds__(256) void block_jacobi_kernel(int n_act, const int *__restrict__ bnd_of,
                                                            const T *__restrict__ Bint_t,
                                                            const T *__restrict__ Bbnd_t, const T *__restrict__ r,
-                                                           T *__restrict__ d, T *__restrict__ z, T alpha, T beta) {
+                                                           T *__restrict__ d, T *__restrict__ z, T alpha, T beta,
+                                                           const int *__restrict__ list) {
     constexpr int CPW = 64 / NC;                 // cells per wave
     __shared__ T rs[4 * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = lane / NC, i = lane % NC;
-    const int K = (blockIdx.x * 4 + wave) * CPW + c;
-    const bool live = c < CPW && K < n_act;
+    const int kx = (blockIdx.x * 4 + wave) * CPW + c;   // cell, or position in the list
+    const bool live = c < CPW && kx < n_act;
+    const int K = list != nullptr ? (live ? list[kx] : 0) : kx;
     const int Kc = live ? K : 0;
     T ri = live ? r[(size_t)Kc * NC + i] : T(0);
     const int bo = live ? bnd_of[Kc] : -1;
@@ -1397,14 +1399,14 @@ __global__ __launch_bounds__(256) void block_jacobi_kernel(int n_act, const int 
 
 template <typename T>
 int launch_block_jacobi(int n_act, int nc, const int *bnd_of, const T *Bint_t, const T *Bbnd_t, const T *r, T *d,
-                        T *z, T alpha, T beta, hipStream_t st) {
+                        T *z, T alpha, T beta, hipStream_t st, const int *list) {
     if (n_act <= 0) return 0;
     const int cpw = 64 / nc;
     const dim3 g((n_act + 4 * cpw - 1) / (4 * cpw)), bl(256);
 #define BJ_CASE(NCV)                                                                                               \
     case NCV:                                                                                                      \
         hipLaunchKernelGGL((block_jacobi_kernel<T, NCV>), g, bl, 0, st, n_act, bnd_of, Bint_t, Bbnd_t, r, d, z,   \
-                           alpha, beta);                                                                           \
+                           alpha, beta, list);                                                                     \
         break;
     switch (nc) {
         BJ_CASE(4)
@@ -1420,9 +1422,9 @@ int launch_block_jacobi(int n_act, int nc, const int *bnd_of, const T *Bint_t, c
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template int launch_block_jacobi<double>(int, int, const int *, const double *, const double *, const double *,
-                                         double *, double *, double, double, hipStream_t);
+                                         double *, double *, double, double, hipStream_t, const int *);
 template int launch_block_jacobi<float>(int, int, const int *, const float *, const float *, const float *, float *,
-                                        float *, float, float, hipStream_t);
+                                        float *, float, float, hipStream_t, const int *);
 
 // --------------------------------------------------------------------------
 template <typename T>

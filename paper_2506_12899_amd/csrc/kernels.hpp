@@ -87,6 +87,11 @@ int launch_pencil(int d, int p, int op, int ncells, const int *cells, const T *x
 template <typename T>
 int launch_pencil_rr(int d, int p, int ncells, const int *cells, const T *x, const T *b, T *bc, T *zc,
                      const CellArgs<T> &a, const KRef<T> &R, const TransferArgs<T> &tr, hipStream_t st);
+// one block-Jacobi step d_K = alpha d_K + beta B_int r_K, z_K += d_K on the
+// listed interior cells (d not read when alpha = 0)
+template <typename T>
+int launch_pencil_bj(int d, int p, int ncells, const int *cells, const T *r, T *dv, T *z, const T *Bint_t, T alpha,
+                     T beta, hipStream_t st);
 // the zero-start colour-0 update z_K = omega B_int b_K on the listed interior cells
 template <typename T, typename TB>
 int launch_pencil_zero(int d, int p, int ncells, const int *cells, const TB *b, T *z, const T *Bint_t, T omega,
@@ -130,7 +135,7 @@ int launch_fill(long long n, T *x, T v, hipStream_t st);
 // when z is given.  B_K: the cell's (transposed) inverse.
 template <typename T>
 int launch_block_jacobi(int n_act, int nc, const int *bnd_of, const T *Bint_t, const T *Bbnd_t, const T *r, T *d,
-                        T *z, T alpha, T beta, hipStream_t st);
+                        T *z, T alpha, T beta, hipStream_t st, const int *list = nullptr);
 int launch_cast_d2f(long long n, const double *x, float *y, hipStream_t st);
 int launch_cast_f2d(long long n, const float *x, double *y, hipStream_t st);
 // Gram-Schmidt kernels.  Partial-sum buffers hold gs_partials_max() doubles;

@@ -547,13 +547,18 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_kernel(int ncells, 
     }
 }
 
-// First colour-0 update from z = 0 on the listed interior cells: the residual
-// is b itself, z_K = omega B_int b_K (b read in its own precision TB).
-template <int P, typename T, typename TB>
+// Block products with the shared inverse on the listed interior cells.
+// BJ = false: the first colour-0 update from z = 0, whose residual is b
+// itself: z_K = omega B_int b_K (b read in its own precision TB).
+// BJ = true: one block-Jacobi step of the Chebyshev smoother (Sec. 3.1
+// additive variant) from the residual r = b: d_K = alpha d_K + omega B_int r_K
+// (d not read when alpha = 0), z_K += d_K.
+template <int P, typename T, typename TB, bool BJ>
 __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int ncells, const int *__restrict__ cells,
                                                                           const TB *__restrict__ b,
                                                                           T *__restrict__ z,
-                                                                          const T *__restrict__ Bint_t, T omega) {
+                                                                          const T *__restrict__ Bint_t, T omega,
+                                                                          T *__restrict__ dv, T alpha) {
     using S = PSh<P>;
     constexpr int N1 = S::N1, NP = S::NP, NC = S::NC, CPW = S::CPW;
     constexpr bool FULL = CPW * NP == 64;
@@ -598,7 +603,16 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
         if (ccell >= 0) {
             const size_t o = (size_t)ccell * NC + 16 * wave;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) z[o + Tile16<T>::row(lane / 16, r)] = T(0) + omega * acc[r];
+            for (int r = 0; r < 4; ++r) {
+                const size_t g = o + Tile16<T>::row(lane / 16, r);
+                if constexpr (BJ) {
+                    const T dn = alpha == T(0) ? omega * acc[r] : alpha * dv[g] + omega * acc[r];
+                    dv[g] = dn;
+                    z[g] += dn;
+                } else {
+                    z[g] = T(0) + omega * acc[r];
+                }
+            }
         }
         return;
     }
@@ -612,7 +626,16 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
     interior_correction<P, T, SBL>(sB, Bint_t, sr + PLayout<P>::at(lc, 0), q, corr);
     if (live) {
 #pragma unroll
-        for (int c = 0; c < N1; ++c) z[(size_t)cell * NC + q + NP * c] = T(0) + omega * corr[c];
+        for (int c = 0; c < N1; ++c) {
+            const size_t g = (size_t)cell * NC + q + NP * c;
+            if constexpr (BJ) {
+                const T dn = alpha == T(0) ? omega * corr[c] : alpha * dv[g] + omega * corr[c];
+                dv[g] = dn;
+                z[g] += dn;
+            } else {
+                z[g] = T(0) + omega * corr[c];
+            }
+        }
     }
 }
 
@@ -670,15 +693,36 @@ int launch_pencil_zero(int d, int p, int ncells, const int *cells, const TB *b, 
     if (!pencil_supported(d, p) || cells == nullptr) return -1;
     if (p == 3) {
         using S = PSh<3>;
-        hipLaunchKernelGGL((pencil_zero_kernel<3, T, TB>), dim3((ncells + S::CPB - 1) / S::CPB), dim3(64 * S::WAVES), 0,
-                           st, ncells, cells, b, z, Bint_t, omega);
+        hipLaunchKernelGGL((pencil_zero_kernel<3, T, TB, false>), dim3((ncells + S::CPB - 1) / S::CPB),
+                           dim3(64 * S::WAVES), 0, st, ncells, cells, b, z, Bint_t, omega, (T *)nullptr, T(0));
     } else {
         using S = PSh<2>;
-        hipLaunchKernelGGL((pencil_zero_kernel<2, T, TB>), dim3((ncells + S::CPB - 1) / S::CPB), dim3(64 * S::WAVES), 0,
-                           st, ncells, cells, b, z, Bint_t, omega);
+        hipLaunchKernelGGL((pencil_zero_kernel<2, T, TB, false>), dim3((ncells + S::CPB - 1) / S::CPB),
+                           dim3(64 * S::WAVES), 0, st, ncells, cells, b, z, Bint_t, omega, (T *)nullptr, T(0));
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+
+template <typename T>
+int launch_pencil_bj(int d, int p, int ncells, const int *cells, const T *r, T *dv, T *z, const T *Bint_t, T alpha,
+                     T beta, hipStream_t st) {
+    if (ncells <= 0) return 0;
+    if (!pencil_supported(d, p) || cells == nullptr || dv == nullptr || z == nullptr) return -1;
+    if (p == 3) {
+        using S = PSh<3>;
+        hipLaunchKernelGGL((pencil_zero_kernel<3, T, T, true>), dim3((ncells + S::CPB - 1) / S::CPB),
+                           dim3(64 * S::WAVES), 0, st, ncells, cells, r, z, Bint_t, beta, dv, alpha);
+    } else {
+        using S = PSh<2>;
+        hipLaunchKernelGGL((pencil_zero_kernel<2, T, T, true>), dim3((ncells + S::CPB - 1) / S::CPB),
+                           dim3(64 * S::WAVES), 0, st, ncells, cells, r, z, Bint_t, beta, dv, alpha);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template int launch_pencil_bj<double>(int, int, int, const int *, const double *, double *, double *, const double *,
+                                      double, double, hipStream_t);
+template int launch_pencil_bj<float>(int, int, int, const int *, const float *, float *, float *, const float *, float,
+                                     float, hipStream_t);
 template int launch_pencil_zero<double, double>(int, int, int, const int *, const double *, double *, const double *,
                                                 double, hipStream_t);
 template int launch_pencil_zero<float, float>(int, int, int, const int *, const float *, float *, const float *, float,

@@ -422,6 +422,16 @@ int resid_restrict(sbm_problem *pb, int l, const T *z, const T *b, T *bc, T *zc 
                                           zc != nullptr ? &zb : nullptr, false));
         KCHK(launch_pencil_rr<T>(Df.d, Df.p, Df.n_int1, Df.pen_col + Df.n_int0, z, b, bc, zc, ca, Df.kref, tr,
                                  pb->stream));
+    } else if (Df.pencil && nch == 1 && zc == nullptr && pb->opt.smoother == 1) {
+        // the Chebyshev cycle (transfers never fused): every cell, boundary
+        // cells by the cell kernel on their list, interior cells by the pencil
+        // kernel.  (The SSOR cycle keeps one kernel for this step whether its
+        // transfers are fused or not: the two forms share their arithmetic.)
+        if (Df.n_bl0 + Df.n_bl1 > 0)
+            KCHK(launch_resid_restrict<T>(Df.d, Df.p, Df.n_bl0 + Df.n_bl1, 1, Dc.p + 1, Df.bnd_list, Df.bnd_list, z, b,
+                                          bc, ca, Df.kref, tr, pb->stream, nullptr, false));
+        KCHK(launch_pencil_rr<T>(Df.d, Df.p, Df.n_int0 + Df.n_int1, Df.pen_all, z, b, bc, nullptr, ca, Df.kref, tr,
+                                 pb->stream));
     } else {
         KCHK(launch_resid_restrict<T>(Df.d, Df.p, Dc.n_act, nch, Dc.p + 1, nch == 1 ? nullptr : Df.rr_perm,
                                       nch == 1 ? nullptr : Df.rr_grp, z, b, bc, ca, Df.kref, tr, pb->stream,
@@ -550,8 +560,16 @@ int cheb_smooth(sbm_problem *pb, int l, const T *b, T *z, bool from_zero) {
             beta = 2.0 * rho / delta;
             rho_old = rho;
         }
-        KCHK(launch_block_jacobi<T>(D.n_act, D.nc, D.bnd_of, D.Bint_t, D.Bbnd_t, r, D.dcheb, z, (T)alpha, (T)beta,
-                                    pb->stream));
+        if (D.pencil) {
+            // boundary cells on their list, interior cells by the pencil kernel
+            KCHK(launch_block_jacobi<T>(D.n_bl0 + D.n_bl1, D.nc, D.bnd_of, D.Bint_t, D.Bbnd_t, r, D.dcheb, z, (T)alpha,
+                                        (T)beta, pb->stream, D.bnd_list));
+            KCHK(launch_pencil_bj<T>(D.d, D.p, D.n_int0 + D.n_int1, D.pen_all, r, D.dcheb, z, D.Bint_t, (T)alpha,
+                                     (T)beta, pb->stream));
+        } else {
+            KCHK(launch_block_jacobi<T>(D.n_act, D.nc, D.bnd_of, D.Bint_t, D.Bbnd_t, r, D.dcheb, z, (T)alpha, (T)beta,
+                                        pb->stream));
+        }
     }
     return SBM_OK;
 }
