@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "time-to-1e-8 rel. residual (s) + DG-apply MDoF/s; FP32/learned vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
 # the cell kernels' sources: HBM counters taken on other versions are not used
-KERNEL_SOURCES = ("kernels.hip", "pencil.hip")
+KERNEL_SOURCES = ("kernels.hip", "pencil.hip", "pencil_body.hpp")
 
 
 def apply_bytes(pb, fp32):
@@ -358,11 +358,12 @@ def main():
     # dominant operation of the timed (FP32 V-cycle) solve: the finest-level
     # colour update, the largest share of the solve's kernel time (on the 96^3 Q3
     # sphere about a quarter of the FP32 solve with its FP64-writing form; the
-    # FP64 Gram-Schmidt sweeps come next).  On 3D Q2/Q3 levels it is one call of
-    # two launches, the pencil kernel on the interior cells and the cell kernel on
-    # the boundary cells; the time is the call's, the bytes the whole colour's.
-    roof = {"bound": "hbm", "kernel": ("finest-level colour update, FP32: pencil_kernel<OP_SMOOTH> (interior cells) "
-                                       "+ cellop_kernel<OP_SMOOTH> (boundary cells)"
+    # FP64 Gram-Schmidt sweeps come next).  On 3D Q2/Q3 levels it is one launch
+    # whose blocks take the boundary cells one thread per DoF and the interior
+    # cells in the pencil form; the bytes are the whole colour's.  (The FP64
+    # apply there is two launches, timed as one call.)
+    roof = {"bound": "hbm", "kernel": ("finest-level colour update, FP32: fused_cell_kernel<OP_SMOOTH> (one launch: "
+                                       "boundary cells one thread per DoF, interior cells in the pencil form)"
                                        if pb.dim == 3 and pb.p >= 2 else "cellop_kernel<OP_SMOOTH> (finest-level colour update, FP32)"),
             "achieved": gbs_s, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs_s / HBM_PEAK_GBS,
             "traffic": counter_traffic(prob.name, "smooth_fp32"), "bytes_per_launch": bs32,

@@ -22,6 +22,7 @@
 
 #include "kernels.hpp"
 #include "device_util.hpp"
+#include "pencil_body.hpp"
 
 namespace sbm {
 
@@ -670,6 +671,99 @@ __attribute__((amdgpu_waves_per_eu(cell_min_waves<D, P, T, OP, EMIT>(), 8))) voi
     cell_batch<D, P, T, OP, S::WAVES, EMIT, typename EmitParam<T, EMIT>::type, NoHook, decltype(stage)>(
         L, sB, bstart, bend, xin, out, b, a, sR, a.perm, e, sP, NoHook(), stage);
 }
+
+// A whole-level operation (apply, residual) or a colour update of a 3D Q2/Q3
+// level in one launch (FP32; the FP64 forms run as two launches, whose
+// separate register budgets measured faster): its first nb_bnd blocks take the boundary cells
+// (bcells, one thread per DoF, four waves per block), the others the interior
+// cells (pcells, the pencil form).  The boundary blocks come first, so that
+// their longer dependent chains start early and the interior blocks fill the
+// machine around them; nb_bnd is a multiple of 8, so the interior blocks keep
+// the XCD-contiguous order.  The two kinds of block never share a block, so
+// their LDS is one union.
+template <int P, typename T, int OP>
+struct FusedCellLds {
+    CellLds<3, P, T, 4> L;
+    KRef<T> sR;
+};
+template <int P, typename T, int OP>
+union FusedLds {
+    PencilShared<P, T, OP> p;
+    FusedCellLds<P, T, OP> c;
+};
+
+// occupancy floor for the FP32 forms (5 waves per SIMD, both parts within
+// 102 VGPRs without a spill); the FP64 forms would spill
+template <int P, typename T>
+constexpr int fused_min_waves() {
+    return sizeof(T) == 4 ? 5 : 1;
+}
+
+template <int P, typename T, int OP, int EMIT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_min_waves<P, T>(), 8))) void fused_cell_kernel(int nb_bnd, int nbnd, const int *__restrict__ bcells,
+                                                         int npen, const int *__restrict__ pcells, const T *xin,
+                                                         T *out, const T *__restrict__ b, CellArgs<T> a, KRef<T> R,
+                                                         typename EmitParam<T, EMIT>::type e) {
+    static_assert(EMIT == EMIT_NONE || EMIT == EMIT_F64, "the pencil form sends values on in FP64 only");
+    __shared__ FusedLds<P, T, OP> U;
+    const int blk = blockIdx.x;
+    if (blk < nb_bnd) {
+        constexpr int NW = 4, CPB = Sh<3, P>::CPW * NW;
+        Stager<(int)(sizeof(KRef<T>) / 4), 64 * NW> kst;
+        kst.load(&R);
+        auto stage = [&]() { kst.store(&U.c.sR); };
+        cell_batch<3, P, T, OP, NW, EMIT, typename EmitParam<T, EMIT>::type, NoHook, decltype(stage)>(
+            U.c.L, nullptr, blk * CPB, nbnd, xin, out, b, a, U.c.sR, bcells, e, nullptr, NoHook(), stage);
+    } else {
+        double *z64 = nullptr;
+        if constexpr (EMIT == EMIT_F64) z64 = e.z64;
+        const int nbp = (int)gridDim.x - nb_bnd;
+        pencil_block<P, T, OP, EMIT == EMIT_F64>(xcd_remap(blk - nb_bnd, nbp), U.p, npen, pcells, xin, out, b, a.nbr,
+                                                 a.Bint_t, R, z64, nullptr, nullptr, TransferArgs<T>{});
+    }
+}
+
+template <int P, typename T>
+static int launch_fused_p(int op, int nbnd, const int *bcells, int npen, const int *pcells, const T *x, T *y,
+                          const T *b, const CellArgs<T> &a, const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e) {
+    constexpr int BCPB = Sh<3, P>::CPW * 4;
+    const int nb_bnd = ((nbnd + BCPB - 1) / BCPB + 7) / 8 * 8;
+    const int nb_pen = (npen + PSh<P>::CPB - 1) / PSh<P>::CPB;
+    if (nb_pen == 0 && nbnd == 0) return 0;
+    const dim3 g(nb_bnd + nb_pen), bl(256);
+    const bool f64 = e != nullptr;
+    if (f64 && (e->kind != EMIT_F64 || e->z64 == nullptr || op != OP_SMOOTH)) return -1;
+    if (op == OP_APPLY)
+        hipLaunchKernelGGL((fused_cell_kernel<P, T, OP_APPLY, EMIT_NONE>), g, bl, 0, st, nb_bnd, nbnd, bcells, npen,
+                           pcells, x, y, b, a, R, 0);
+    else if (op == OP_RESID)
+        hipLaunchKernelGGL((fused_cell_kernel<P, T, OP_RESID, EMIT_NONE>), g, bl, 0, st, nb_bnd, nbnd, bcells, npen,
+                           pcells, x, y, b, a, R, 0);
+    else if (op == OP_SMOOTH && !f64)
+        hipLaunchKernelGGL((fused_cell_kernel<P, T, OP_SMOOTH, EMIT_NONE>), g, bl, 0, st, nb_bnd, nbnd, bcells, npen,
+                           pcells, x, y, b, a, R, 0);
+    else if (op == OP_SMOOTH) {
+        if constexpr (std::is_same<T, float>::value)
+            hipLaunchKernelGGL((fused_cell_kernel<P, T, OP_SMOOTH, EMIT_F64>), g, bl, 0, st, nb_bnd, nbnd, bcells,
+                               npen, pcells, x, y, b, a, R, *e);
+        else
+            return -1;
+    } else {
+        return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+int launch_fused(int d, int p, int op, int nbnd, const int *bcells, int npen, const int *pcells, const T *x, T *y,
+                 const T *b, const CellArgs<T> &a, const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e) {
+    if (!pencil_supported(d, p) || (nbnd > 0 && bcells == nullptr) || (npen > 0 && pcells == nullptr)) return -1;
+    return p == 3 ? launch_fused_p<3, T>(op, nbnd, bcells, npen, pcells, x, y, b, a, R, st, e)
+                  : launch_fused_p<2, T>(op, nbnd, bcells, npen, pcells, x, y, b, a, R, st, e);
+}
+template int launch_fused<float>(int, int, int, int, const int *, int, const int *, const float *, float *,
+                                 const float *, const CellArgs<float> &, const KRef<float> &, hipStream_t,
+                                 const EmitArgs<float> *);
 
 // Residual and restriction in one launch (Sec. 3.2: the restriction is the
 // transpose of the embedding); the residual is not written to memory.

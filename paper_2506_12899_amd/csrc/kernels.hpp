@@ -82,6 +82,12 @@ bool pencil_supported(int d, int p);
 template <typename T>
 int launch_pencil(int d, int p, int op, int ncells, const int *cells, const T *x, T *y, const T *b,
                   const CellArgs<T> &a, const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e);
+// the boundary cells (bcells, one thread per DoF) and the interior cells
+// (pcells, pencil form) of a 3D Q2/Q3 level in one launch: OP_APPLY, OP_RESID
+// or OP_SMOOTH (e: null or EMIT_F64); instantiated for FP32
+template <typename T>
+int launch_fused(int d, int p, int op, int nbnd, const int *bcells, int npen, const int *pcells, const T *x, T *y,
+                 const T *b, const CellArgs<T> &a, const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e);
 // residual restricted to the same cells one degree down, bc = E^T (b - A x),
 // and zc = 0 there (when given), on the listed interior cells
 template <typename T>
