@@ -98,6 +98,11 @@ int launch_pencil_rr(int d, int p, int ncells, const int *cells, const T *x, con
 template <typename T>
 int launch_pencil_bj(int d, int p, int ncells, const int *cells, const T *r, T *dv, T *z, const T *Bint_t, T alpha,
                      T beta, hipStream_t st);
+// p-prolongation zf += E zc on every cell of a 3D Q2/Q3 level (parent: the
+// same cell one degree down)
+template <typename T>
+int launch_pencil_prolong(int d, int p, int ncells, const int *parent, const T *zc, T *zf, const TransferArgs<T> &tr,
+                          hipStream_t st);
 // the zero-start colour-0 update z_K = omega B_int b_K on the listed interior cells
 template <typename T, typename TB>
 int launch_pencil_zero(int d, int p, int ncells, const int *cells, const TB *b, T *z, const T *Bint_t, T omega,

@@ -131,6 +131,97 @@ __global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_zero_kernel(int nce
     }
 }
 
+// p-prolongation on every cell of a 3D level of degree P from the same cell
+// one degree down (Sec. 3.2: the embedding E = tr.P1[0] along each
+// direction): zf_K += (E x E x E) zc_parent(K), by sum factorisation along x
+// (lanes of coarse (y, z) lines), y (fine x, coarse z), z (fine x, y: the
+// lane's pencil of the fine cell).
+template <int P, typename T>
+__global__ __launch_bounds__(64 * PSh<P>::WAVES) void pencil_prolong_kernel(int ncells, const int *__restrict__ parent,
+                                                                             const T *__restrict__ zc,
+                                                                             T *__restrict__ zf, TransferArgs<T> tr) {
+    using S = PSh<P>;
+    constexpr int N1 = S::N1, NP = S::NP, NC = S::NC, CPW = S::CPW, N1C = P, NCC = P * P * P;
+    constexpr bool FULL = CPW * NP == 64;
+    __shared__ T s1[S::CPB][N1 * N1C * N1C];   // after x: [fine x][coarse y][coarse z]
+    __shared__ T s2[S::CPB][N1 * N1 * N1C];    // after y: [fine x][fine y][coarse z]
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = lane / NP;
+    const bool inslot = FULL || slot < CPW;
+    const int q = inslot ? lane - slot * NP : 0;
+    const int qa = q % N1, qb = q / N1;
+    const int lc = wave * CPW + (inslot ? slot : 0);
+    const int cell = xcd_remap(blockIdx.x, gridDim.x) * S::CPB + lc;
+    const bool live = inslot && cell < ncells;
+    const int K = live ? cell : 0;
+    const int pc = parent[K];
+    const T *zp = zc + (size_t)(pc < 0 ? 0 : pc) * NCC;
+    // this lane's fine values (its z pencil) are read early, with the coarse line
+    T old[N1];
+#pragma unroll
+    for (int c = 0; c < N1; ++c) old[c] = zf[(size_t)K * NC + q + NP * c];
+    if (inslot && q < N1C * N1C) {
+        T c[N1C];
+#pragma unroll
+        for (int a = 0; a < N1C; ++a) c[a] = zp[a + N1C * q];
+#pragma unroll
+        for (int f = 0; f < N1; ++f) {
+            T acc = 0;
+#pragma unroll
+            for (int a = 0; a < N1C; ++a) acc += tr.P1[0][f][a] * c[a];
+            s1[lc][f + N1 * q] = acc;
+        }
+    }
+    wave_sync();
+    if (inslot && q < N1 * N1C) {
+        const int fx = q % N1, cz = q / N1;
+        T c[N1C];
+#pragma unroll
+        for (int a = 0; a < N1C; ++a) c[a] = s1[lc][fx + N1 * (a + N1C * cz)];
+#pragma unroll
+        for (int f = 0; f < N1; ++f) {
+            T acc = 0;
+#pragma unroll
+            for (int a = 0; a < N1C; ++a) acc += tr.P1[0][f][a] * c[a];
+            s2[lc][fx + N1 * (f + N1 * cz)] = acc;
+        }
+    }
+    wave_sync();
+    T c[N1C];
+#pragma unroll
+    for (int a = 0; a < N1C; ++a) c[a] = s2[lc][qa + N1 * (qb + N1 * a)];
+    if (live && pc >= 0) {
+#pragma unroll
+        for (int f = 0; f < N1; ++f) {
+            T acc = 0;
+#pragma unroll
+            for (int a = 0; a < N1C; ++a) acc += tr.P1[0][f][a] * c[a];
+            zf[(size_t)K * NC + q + NP * f] = old[f] + acc;
+        }
+    }
+}
+
+template <typename T>
+int launch_pencil_prolong(int d, int p, int ncells, const int *parent, const T *zc, T *zf, const TransferArgs<T> &tr,
+                          hipStream_t st) {
+    if (ncells <= 0) return 0;
+    if (!pencil_supported(d, p) || parent == nullptr) return -1;
+    if (p == 3) {
+        using S = PSh<3>;
+        hipLaunchKernelGGL((pencil_prolong_kernel<3, T>), dim3((ncells + S::CPB - 1) / S::CPB), dim3(64 * S::WAVES), 0,
+                           st, ncells, parent, zc, zf, tr);
+    } else {
+        using S = PSh<2>;
+        hipLaunchKernelGGL((pencil_prolong_kernel<2, T>), dim3((ncells + S::CPB - 1) / S::CPB), dim3(64 * S::WAVES), 0,
+                           st, ncells, parent, zc, zf, tr);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template int launch_pencil_prolong<double>(int, int, int, const int *, const double *, double *,
+                                           const TransferArgs<double> &, hipStream_t);
+template int launch_pencil_prolong<float>(int, int, int, const int *, const float *, float *,
+                                          const TransferArgs<float> &, hipStream_t);
+
 template <int P, typename T>
 static int launch_p(int op, int ncells, const int *cells, const T *x, T *y, const T *b, const CellArgs<T> &a,
                     const KRef<T> &R, hipStream_t st, double *z64) {

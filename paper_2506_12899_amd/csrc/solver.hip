@@ -465,6 +465,13 @@ int prolong_add(sbm_problem *pb, int l, const T *zc, T *zf) {
     auto &Dc = devlevels<T>(pb)[l - 1];
     TransferArgs<T> tr;
     std::memcpy(tr.P1, Df.P1, sizeof(tr.P1));
+    if (Df.pencil && Dc.pencil && pb->levels[l].ratio == 1 && Dc.p + 1 == Df.p) {
+        // p-transfer between pencil levels (which never fold it into their
+        // colour updates, so the fused and the separate cycle both come here):
+        // sum factorised, one lane per fine line
+        KCHK(launch_pencil_prolong<T>(Df.d, Df.p, Df.n_act, Df.parent, zc, zf, tr, pb->stream));
+        return SBM_OK;
+    }
     KCHK(launch_prolong<T>(Df.d, Df.n_act, Df.p + 1, Dc.p + 1, Df.parent, Df.childpos, zc, zf, tr, pb->stream));
     return SBM_OK;
 }
