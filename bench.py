@@ -2,14 +2,15 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere96_q3]
 
-One step is one full solve of the hot path -- FGMRES(30) preconditioned by
+One step is one full solve of the hot path -- FGMRES(m) preconditioned by
 the hp-multigrid V-cycle with the red-black cell-block smoother, h/p transfers
 and the FP64 GMRES vector kernels -- from x0 = 0 to ||b - A x|| <= 1e-8 ||b||,
 with the problem already set up and b already resident in HBM.  The timed
 form is the production one (FP32 V-cycle inside FP64 FGMRES); the plain FP64
 solve is timed the same way beside it.  The default workload is the 96^3 Q3
 sphere in its stabilised form (see paper_2506_12899_amd/workloads.py); the 2D
-Q2 star's solve times are added as extra keys.  The dominant kernel's roofline is
+Q2 star's and the 128^3 Q3 union's solve times (the latter with FGMRES(256))
+are added as extra keys.  The dominant kernel's roofline is
 measured live with HIP events on the library's stream, and the CPU oracle is
 timed on the host on the same problem.
 
@@ -252,11 +253,11 @@ def learned_leg(pb, prob, b, x, torch, args, t32, st32):
     train_s = time.perf_counter() - t0
     learned.install(pb, net)
     pb.set_vcycle_fp32(1)
-    _, st = pb.solve(b, x, tol=1e-8, max_iter=args.max_iter)
+    _, st = pb.solve(b, x, tol=1e-8, restart=prob.restart, max_iter=args.max_iter)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, st = pb.solve(b, x, tol=1e-8, max_iter=args.max_iter)
+        _, st = pb.solve(b, x, tol=1e-8, restart=prob.restart, max_iter=args.max_iter)
     torch.cuda.synchronize()
     tl = (time.perf_counter() - t0) / args.steps
     better = st["converged"] and (not st32["converged"] or st["iterations"] < st32["iterations"])
@@ -275,13 +276,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere96_q3")
-    ap.add_argument("--extra", default="star512_q2",
+    ap.add_argument("--extra", default="star512_q2,balls128_q3",
                     help="comma-separated workloads whose solve times are added as extra keys ('' for none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-correction leg (3D Q3 workloads: train, then FP32 + learned solve)")
     ap.add_argument("--apply-reps", type=int, default=200)
-    ap.add_argument("--max-iter", type=int, default=300, help="FGMRES iteration cap (failure beyond it)")
+    ap.add_argument("--max-iter", type=int, default=None,
+                    help="FGMRES iteration cap (failure beyond it; default 300, or 4 restart lengths if longer)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run finest-level applies and colour updates and a plain copy (for profilers)")
     args = ap.parse_args()
@@ -295,6 +297,8 @@ def main():
     from paper_2506_12899_amd.problem import Problem
 
     prob = workloads.problem(args.workload)
+    if args.max_iter is None:
+        args.max_iter = max(300, 4 * prob.restart)
     t0 = time.perf_counter()
     pb = Problem(prob.geometry, prob.n, prob.p, device=0, **prob.opts)
     setup_s = time.perf_counter() - t0
@@ -326,11 +330,11 @@ def main():
         pb.set_vcycle_fp32(fp32)
         st = None
         for _ in range(warmup):
-            _, st = pb.solve(b, x, tol=1e-8, max_iter=args.max_iter)
+            _, st = pb.solve(b, x, tol=1e-8, restart=prob.restart, max_iter=args.max_iter)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            _, st = pb.solve(b, x, tol=1e-8, max_iter=args.max_iter)
+            _, st = pb.solve(b, x, tol=1e-8, restart=prob.restart, max_iter=args.max_iter)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, st
 
@@ -382,7 +386,7 @@ def main():
         "ms_per_step": t32 * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 V-cycle / f64 Krylov", "data": "synthetic",
         "config": {"workload": prob.name, "dim": prob.dim, "n": prob.n, "p": prob.p, "n_dofs": int(pb.n_dofs),
-                   "solver": "FGMRES(30) + hp-MG V(1,1), red-black cell SSOR", "tol": 1e-8,
+                   "solver": f"FGMRES({prob.restart}) + hp-MG V(1,1), red-black cell SSOR", "tol": 1e-8,
                    "options": prob.opts},
         "converged": bool(ok),
         "fp32_iterations": st32["iterations"], "fp32_rel_residual": st32["rel_residual"],
@@ -414,17 +418,24 @@ def main():
         pbe = Problem(pe.geometry, pe.n, pe.p, device=0, **pe.opts)
         be = pbe.rhs(pe.solution.f, pe.solution.u)
         xe = torch.empty_like(be)
-        rec = {"n_dofs": int(pbe.n_dofs)}
+        rec = {"n_dofs": int(pbe.n_dofs), "restart": pe.restart}
+        max_iter_e = max(args.max_iter, 4 * pe.restart)
         for fp32 in (0, 1):
             pbe.set_vcycle_fp32(fp32)
-            pbe.solve(be, xe, tol=1e-8, max_iter=args.max_iter)
             torch.cuda.synchronize()
+            tw = time.perf_counter()
+            pbe.solve(be, xe, tol=1e-8, restart=pe.restart, max_iter=max_iter_e)
+            torch.cuda.synchronize()
+            # solves of seconds are timed fewer times than --steps
+            steps_e = max(1, min(args.steps, int(2.0 / max(time.perf_counter() - tw, 1e-6))))
             t0 = time.perf_counter()
-            for _ in range(args.steps):
-                _, ste = pbe.solve(be, xe, tol=1e-8, max_iter=args.max_iter)
+            for _ in range(steps_e):
+                _, ste = pbe.solve(be, xe, tol=1e-8, restart=pe.restart, max_iter=max_iter_e)
             torch.cuda.synchronize()
             key = "fp32" if fp32 else "fp64"
-            rec[f"{key}_s"] = (time.perf_counter() - t0) / args.steps
+            rec[f"{key}_s"] = (time.perf_counter() - t0) / steps_e
+            rec[f"{key}_steps"] = steps_e
+            rec[f"{key}_rel_residual"] = ste["rel_residual"]
             rec[f"{key}_iterations"] = ste["iterations"]
             rec[f"{key}_converged"] = bool(ste["converged"])
         extra[name] = rec

@@ -211,12 +211,18 @@ int sbm_apply(struct sbm_problem *pb, const void *x_dev, void *y_dev, int fp32);
  * the whole cycle (blocks stored in that precision).  Asynchronous. */
 int sbm_vcycle(struct sbm_problem *pb, const void *r_dev, void *z_dev, int fp32);
 
+/* Longest FGMRES restart sbm_solve and sbm_solve_noalloc accept. */
+#define SBM_MAX_RESTART 256
+
 /* Solve A x = b with FGMRES(restart), right-preconditioned by one V-cycle
  * (FP32 if o->vcycle_fp32), FP64 Arnoldi (classical Gram-Schmidt, second pass
- * only when the first cancels: |w'| < 0.1 |w|), x0 = 0; stops when the TRUE
+ * only when the first cancels, |w'| < 0.1 |w|, when tol < 1e-10, or for basis
+ * vectors beyond the 30th), x0 = 0; stops when the TRUE
  * relative residual ||b - A x|| / ||b|| <= tol, or after max_iter
  * iterations (then SBM_NOT_CONVERGED, x holds the last iterate).  b, x: FP64
- * device vectors.  Synchronous.  st may be NULL. */
+ * device vectors; restart in 1..SBM_MAX_RESTART (else SBM_EINVAL); the
+ * workspace holds 2 restart + 2 vectors of n_dofs.  Synchronous.  st may be
+ * NULL. */
 int sbm_solve(struct sbm_problem *pb, const double *b_dev, double *x_dev, double tol, int restart,
               int max_iter, sbm_stats *st);
 

@@ -152,6 +152,15 @@ struct CoarseDev {
     double *Ainv64 = nullptr;   // dense inverse, used by the FP64 and the FP32 cycle
 };
 
+// Device scalars of one FGMRES solve (the pinned staging buffer has the same
+// size): three sum areas of SBM_MAX_RESTART + 1 (Gram-Schmidt pass 1, pass 2,
+// explicit norm), the least-squares coefficients and beta^2.
+constexpr int SOLVE_SCALARS = 4 * (SBM_MAX_RESTART + 1) + 1;
+// Host Arnoldi storage: Hessenberg matrix, Givens cosines and sines, reduced
+// right-hand side, coefficients.
+constexpr size_t ARNOLDI_DOUBLES =
+    (size_t)(SBM_MAX_RESTART + 1) * SBM_MAX_RESTART + 4 * (size_t)SBM_MAX_RESTART + 1;
+
 }  // namespace sbm
 
 // The opaque problem handle.
@@ -170,7 +179,8 @@ struct sbm_problem {
     double *V = nullptr, *Z = nullptr, *w = nullptr, *red = nullptr, *hdev = nullptr;
     double *r32in = nullptr;   // unused placeholder for alignment
     float *f32_in = nullptr, *f32_out = nullptr;   // FP32 cycle in/out on the finest level
-    double *pinned = nullptr;  // host staging for reductions
+    double *pinned = nullptr;  // host staging for reductions (SOLVE_SCALARS)
+    std::vector<double> arnoldi;  // ARNOLDI_DOUBLES, sized at setup
     std::vector<void *> allocations;
     std::string last_error;
     bool host_only = false;    // set up with device < 0: host data only (tests)

@@ -953,7 +953,8 @@ static int setup_body(const sbm_geometry *g, int n, int p, const sbm_options *o,
         *out = pb;
         return rc;
     }
-    if (hipHostMalloc((void **)&pb->pinned, 256 * sizeof(double)) != hipSuccess) {
+    pb->arnoldi.assign(sbm::ARNOLDI_DOUBLES, 0.0);
+    if (hipHostMalloc((void **)&pb->pinned, sbm::SOLVE_SCALARS * sizeof(double)) != hipSuccess) {
         *out = pb;
         return SBM_ENOMEM;
     }
@@ -1295,11 +1296,56 @@ struct SolveWork {
     double *V = nullptr, *Z = nullptr, *w = nullptr, *red = nullptr, *hdev = nullptr;
 };
 
-static constexpr int MAX_RESTART = 30;
+static constexpr int MAX_RESTART = SBM_MAX_RESTART;
+// offsets into the device scalars (and the pinned staging buffer)
+static constexpr int HD_P1 = 0;                         // pass-1 sums: V^T w, then |w|^2
+static constexpr int HD_P2 = MAX_RESTART + 1;           // pass-2 sums
+static constexpr int HD_P3 = 2 * (MAX_RESTART + 1);     // explicit norm pass / true residual
+static constexpr int HD_Y = 3 * (MAX_RESTART + 1);      // least-squares coefficients
+static constexpr int HD_BETA = 4 * (MAX_RESTART + 1);   // beta^2
+static_assert(HD_BETA + 1 == sbm::SOLVE_SCALARS, "device scalar layout");
+
+// One Gram-Schmidt launch sums at most GS_CHUNK basis vectors (plus the norm
+// slot).  Longer bases run chunk by chunk through the same launches; bases of
+// up to GS_CHUNK vectors take the single launches, so restarts up to 31 keep
+// their arithmetic.
+static constexpr int GS_CHUNK = 31;
+
+// out[i] = V_i . w (i < nv), out[nv] = w . w.  Each chunk's reduction also
+// writes its norm slot, which the next chunk's first sum overwrites.
+static int gs_project(sbm_problem *pb, long long n, int nv, const double *V, const double *w, double *part,
+                      double *out, hipStream_t s) {
+    for (int c0 = 0; c0 < nv; c0 += GS_CHUNK) {
+        const int mc = std::min(GS_CHUNK, nv - c0);
+        KCHK(launch_gs_dots(n, mc, V + (size_t)c0 * n, w, part, s));
+        KCHK(launch_gs_reduce(n, mc + 1, part, out + c0, s));
+    }
+    return SBM_OK;
+}
+
+// w -= sum_{i < nv} h[i] V_i, in place
+static int gs_subtract(sbm_problem *pb, long long n, int nv, const double *V, const double *h, double *w,
+                       hipStream_t s) {
+    for (int c0 = 0; c0 < nv; c0 += GS_CHUNK)
+        KCHK(launch_multiaxpy(n, std::min(GS_CHUNK, nv - c0), -1.0, h + c0, V + (size_t)c0 * n, w, s));
+    return SBM_OK;
+}
+
+// v = (w - sum_{i < nv} h[i] V_i) * inv; the leading chunks of a long basis
+// are subtracted from w in place first
+static int gs_subtract_scale(sbm_problem *pb, long long n, int nv, const double *V, const double *h, double inv,
+                             double *w, double *v, hipStream_t s) {
+    const int last = (nv - 1) / GS_CHUNK * GS_CHUNK;
+    int rc;
+    if (last > 0 && (rc = gs_subtract(pb, n, last, V, h, w, s))) return rc;
+    KCHK(launch_gs_axpy_scale(n, nv - last, V + (size_t)last * n, h + last, inv, w, v, s));
+    return SBM_OK;
+}
 
 static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st,
                       const SolveWork &ws) {
-    if (!pb || pb->host_only || !b || !x || b == x || m < 1 || m > MAX_RESTART || max_iter < 1 || !(tol > 0))
+    if (!pb || pb->host_only || !b || !x || b == x || m < 1 || m > MAX_RESTART || max_iter < 1 || !(tol > 0) ||
+        !pb->pinned || pb->arnoldi.size() < sbm::ARNOLDI_DOUBLES)
         return SBM_EINVAL;
     auto t0 = std::chrono::steady_clock::now();
     const HostLevel &L = pb->levels.back();
@@ -1326,10 +1372,12 @@ static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, i
         HIPCHK(hipStreamSynchronize(s));
         return SBM_OK;
     }
-    // Hessenberg matrix, Givens rotations and the reduced right-hand side on
-    // the stack (m <= MAX_RESTART): the solve allocates nothing on the host
-    double H[(MAX_RESTART + 1) * MAX_RESTART], cs[MAX_RESTART], sn[MAX_RESTART], gv[MAX_RESTART + 1],
-        y[MAX_RESTART];
+    // Hessenberg matrix (row stride m), Givens rotations, the reduced
+    // right-hand side and the coefficients in the problem's own storage, sized
+    // for MAX_RESTART at setup: the solve allocates nothing on the host
+    double *H = pb->arnoldi.data();
+    double *cs = H + (size_t)(MAX_RESTART + 1) * MAX_RESTART, *sn = cs + MAX_RESTART, *gv = sn + MAX_RESTART,
+           *y = gv + MAX_RESTART + 1;
     // r = b (x0 = 0); v0 = r / ||r||
     HIPCHK(hipMemcpyAsync(w, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     double beta = nb;
@@ -1337,11 +1385,9 @@ static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, i
     double rel = 1.0;
     int status = SBM_NOT_CONVERGED;
     for (;;) {
-        hp[0] = beta * beta;
-        // device scratch hd: [0,32) CGS pass 1, [32,64) pass 2, [64,96) explicit norm, [96,126) y,
-        // 127 beta^2
-        HIPCHK(hipMemcpyAsync(hd + 127, hp, sizeof(double), hipMemcpyHostToDevice, s));
-        KCHK(launch_scale(n, hd + 127, w, V, s));
+        hp[HD_BETA] = beta * beta;
+        HIPCHK(hipMemcpyAsync(hd + HD_BETA, hp + HD_BETA, sizeof(double), hipMemcpyHostToDevice, s));
+        KCHK(launch_scale(n, hd + HD_BETA, w, V, s));
         std::fill(H, H + (size_t)(m + 1) * m, 0.0);
         std::fill(gv, gv + m + 1, 0.0);
         gv[0] = beta;
@@ -1384,12 +1430,19 @@ static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, i
             // Arnoldi residual estimate (measured on the paper's 2D disk at
             // 1e-12: 33 iterations against 18 with the norm measured), so
             // there every step takes the second pass and measures |w''|.
+            // The one-pass step's loss of orthogonality compounds along the
+            // basis (about eps times the square of the residual reduction
+            // within the cycle): harmless over 30 vectors, but on a weakly
+            // preconditioned 2D disk the basis drifts 1e-6 from orthogonal by
+            // vector 40 and 0.16 by vector 80, and the residual estimate then
+            // stalls (FGMRES(100): 100 iterations against 87).  Vectors beyond
+            // the 30th therefore always take the second pass.
             constexpr double eta = 0.1;
+            constexpr int one_pass_max = 30;
             const bool norm_identity = tol >= 1e-10;
             const int nv = j + 1;
             double *vnext = V + (size_t)(j + 1) * n;
-            KCHK(launch_gs_dots(n, nv, V, w, pa, s));
-            KCHK(launch_gs_reduce(n, nv + 1, pa, hd, s));
+            if ((rc = gs_project(pb, n, nv, V, w, pa, hd + HD_P1, s))) return rc;
             HIPCHK(hipMemcpyAsync(hp, hd, (size_t)(nv + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             double h1sq = 0.0;
@@ -1397,32 +1450,45 @@ static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, i
             const double wsq = hp[nv];
             if (!std::isfinite(wsq) || !std::isfinite(h1sq)) return SBM_ENONFINITE;
             double hn;
-            if (norm_identity && wsq - h1sq >= eta * eta * wsq) {
+            if (norm_identity && nv <= one_pass_max && wsq - h1sq >= eta * eta * wsq) {
                 for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hp[i];
                 hn = std::sqrt(wsq - h1sq);
-                KCHK(launch_gs_axpy_scale(n, nv, V, hd, hn > 0.0 ? 1.0 / hn : 1.0, w, vnext, s));
+                if ((rc = gs_subtract_scale(pb, n, nv, V, hd + HD_P1, hn > 0.0 ? 1.0 / hn : 1.0, w, vnext, s)))
+                    return rc;
             } else {
-                KCHK(launch_gs_axpy_dots(n, nv, V, pa, hd, w, pq, s));
-                KCHK(launch_gs_reduce(n, nv + 1, pq, hd + 32, s));
-                HIPCHK(hipMemcpyAsync(hp + 32, hd + 32, (size_t)(nv + 1) * sizeof(double), hipMemcpyDeviceToHost,
-                                      s));
+                if (nv <= GS_CHUNK) {
+                    KCHK(launch_gs_axpy_dots(n, nv, V, pa, hd + HD_P1, w, pq, s));
+                    KCHK(launch_gs_reduce(n, nv + 1, pq, hd + HD_P2, s));
+                } else if ((rc = gs_subtract(pb, n, nv, V, hd + HD_P1, w, s)) ||
+                           (rc = gs_project(pb, n, nv, V, w, pq, hd + HD_P2, s))) {
+                    return rc;
+                }
+                HIPCHK(hipMemcpyAsync(hp + HD_P2, hd + HD_P2, (size_t)(nv + 1) * sizeof(double),
+                                      hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
-                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hp[i] + hp[32 + i];
+                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hp[i] + hp[HD_P2 + i];
                 double h2sq = 0.0;
-                for (int i = 0; i <= j; ++i) h2sq += hp[32 + i] * hp[32 + i];
-                const double w1sq = hp[32 + nv];
+                for (int i = 0; i <= j; ++i) h2sq += hp[HD_P2 + i] * hp[HD_P2 + i];
+                const double w1sq = hp[HD_P2 + nv];
                 if (!std::isfinite(w1sq) || !std::isfinite(h2sq)) return SBM_ENONFINITE;
                 if (h2sq <= 0.5 * w1sq) {
                     hn = std::sqrt(w1sq - h2sq);
-                    KCHK(launch_gs_axpy_scale(n, nv, V, hd + 32, hn > 0.0 ? 1.0 / hn : 1.0, w, vnext, s));
+                    if ((rc = gs_subtract_scale(pb, n, nv, V, hd + HD_P2, hn > 0.0 ? 1.0 / hn : 1.0, w, vnext,
+                                                s)))
+                        return rc;
                 } else {
-                    KCHK(launch_gs_axpy_dots(n, nv, V, pq, hd + 64, w, pa, s));
-                    KCHK(launch_gs_reduce(n, nv + 1, pa, hd + 64, s));
-                    HIPCHK(hipMemcpyAsync(hp + 64, hd + 64 + nv, sizeof(double), hipMemcpyDeviceToHost, s));
+                    if (nv <= GS_CHUNK) {
+                        KCHK(launch_gs_axpy_dots(n, nv, V, pq, hd + HD_P3, w, pa, s));
+                        KCHK(launch_gs_reduce(n, nv + 1, pa, hd + HD_P3, s));
+                    } else if ((rc = gs_subtract(pb, n, nv, V, hd + HD_P2, w, s)) ||
+                               (rc = gs_project(pb, n, nv, V, w, pa, hd + HD_P3, s))) {
+                        return rc;
+                    }
+                    HIPCHK(hipMemcpyAsync(hp + HD_P3, hd + HD_P3 + nv, sizeof(double), hipMemcpyDeviceToHost, s));
                     HIPCHK(hipStreamSynchronize(s));
-                    hn = std::sqrt(hp[64]);
+                    hn = std::sqrt(hp[HD_P3]);
                     if (!std::isfinite(hn)) return SBM_ENONFINITE;
-                    KCHK(launch_scale(n, hd + 64 + nv, w, vnext, s));
+                    KCHK(launch_scale(n, hd + HD_P3 + nv, w, vnext, s));
                 }
             }
             H[(size_t)(j + 1) * m + j] = hn;
@@ -1452,14 +1518,15 @@ static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, i
             for (int k2 = i + 1; k2 < j; ++k2) acc -= H[(size_t)i * m + k2] * y[k2];
             y[i] = acc / H[(size_t)i * m + i];
         }
-        for (int i = 0; i < j; ++i) hp[i] = y[i];
-        HIPCHK(hipMemcpyAsync(hd + 96, hp, j * sizeof(double), hipMemcpyHostToDevice, s));
-        KCHK(launch_multiaxpy(n, j, 1.0, hd + 96, Z, x, s));
+        for (int i = 0; i < j; ++i) hp[HD_Y + i] = y[i];
+        HIPCHK(hipMemcpyAsync(hd + HD_Y, hp + HD_Y, j * sizeof(double), hipMemcpyHostToDevice, s));
+        for (int c0 = 0; c0 < j; c0 += GS_CHUNK)
+            KCHK(launch_multiaxpy(n, std::min(GS_CHUNK, j - c0), 1.0, hd + HD_Y + c0, Z + (size_t)c0 * n, x, s));
         // true residual
         if ((rc = level_apply<double>(pb, lf, OP_RESID, x, w, b))) return rc;
         KCHK(launch_gs_dots(n, 0, nullptr, w, pa, s));
-        KCHK(launch_gs_reduce(n, 1, pa, hd + 64, s));
-        HIPCHK(hipMemcpyAsync(hp, hd + 64, sizeof(double), hipMemcpyDeviceToHost, s));
+        KCHK(launch_gs_reduce(n, 1, pa, hd + HD_P3, s));
+        HIPCHK(hipMemcpyAsync(hp, hd + HD_P3, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         beta = std::sqrt(hp[0]);
         if (!std::isfinite(beta)) return SBM_ENONFINITE;
@@ -1490,7 +1557,7 @@ int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, in
             if ((rc = dalloc(pb, &pb->V, (size_t)(m + 1) * n)) || (rc = dalloc(pb, &pb->Z, (size_t)m * n)) ||
                 (rc = dalloc(pb, &pb->w, (size_t)n)) ||
                 (rc = dalloc(pb, &pb->red, (size_t)2 * sbm::gs_partials_max())) ||
-                (rc = dalloc(pb, &pb->hdev, (size_t)128)))
+                (rc = dalloc(pb, &pb->hdev, (size_t)sbm::SOLVE_SCALARS)))
                 return rc;
             pb->ws_restart = m;
         }
@@ -1553,7 +1620,8 @@ long long sbm_solve_noalloc_doubles(const sbm_problem *pb, int m) {
     const HostLevel &L = pb->levels.back();
     const long long n = (long long)L.n_act * L.nc;
     auto up = [](long long k) { return (k + 31) / 32 * 32; };   // 256-byte sections
-    return up((long long)(m + 1) * n) + up((long long)m * n) + up(n) + up(2LL * sbm::gs_partials_max()) + up(128);
+    return up((long long)(m + 1) * n) + up((long long)m * n) + up(n) + up(2LL * sbm::gs_partials_max()) +
+           up(sbm::SOLVE_SCALARS);
 }
 
 int sbm_solve_noalloc(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st) {

@@ -341,6 +341,57 @@ def test_solve_with_restarts(fp32):
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("tol", [1e-9, 1e-11])
+def test_solve_long_restart(fp32, tol):
+    """FGMRES(100) on a cycle weakened by omega = 0.05: the oracle takes 87
+    iterations at tol 1e-9 and 115 at 1e-11 (one restart), so the Arnoldi
+    basis runs over three or four 31-vector chunks of the Gram-Schmidt
+    launches (tol 1e-9 takes the norm identity, 1e-11 the second pass with a
+    measured norm).  Against the oracle's FGMRES(100):
+    iteration count, true residual through the oracle's matrix, and x; the
+    allocation-free solve gives the same x."""
+    from paper_2506_12899_amd.problem import Problem
+    dev = _gpu()
+    prob = workloads.problem("disk32_q1")
+    print(f"[parity] long restart fp32={fp32} tol={tol}", flush=True)
+    kw = dict(coarse_dofs=256, omega=0.05)
+    pb = Problem(prob.geometry, prob.n, prob.p, device=0, vcycle_fp32=fp32, **kw)
+    b = pb.rhs(prob.solution.f, prob.solution.u)
+    x, st = pb.solve(b, tol=tol, restart=100, max_iter=300)
+    H = mg.Hierarchy(oracle_geometry(prob.geometry), prob.dim, prob.n, prob.p, **kw)
+    bo = b.cpu().numpy()
+    xo, its_o, _, conv_o, _ = krylov.fgmres(H.fine.apply, H.vcycle, bo, tol=tol, restart=100, max_iter=300)
+    print(f"[parity] long restart: {st['iterations']} its (oracle {its_o})", flush=True)
+    assert conv_o and its_o > 62
+    assert st["converged"] and st["rel_residual"] <= tol
+    # the FP32 cycle is another (FP32-rounded) preconditioner: its count is
+    # held within 10 % of the FP64 oracle's (93 against 87 measured)
+    assert abs(st["iterations"] - its_o) <= (2 if fp32 == 0 else max(4, its_o // 10))
+    xn = x.cpu().numpy()
+    assert np.linalg.norm(bo - H.fine.A @ xn) <= tol * np.linalg.norm(bo) * (1 + 1e-6)
+    assert _rel(xn, xo) <= 1e3 * tol
+    x2, st2 = pb.solve(b, tol=tol, restart=100, max_iter=300, noalloc=True)
+    assert st2["iterations"] == st["iterations"]
+    assert torch.equal(x2, x)
+
+
+def test_solve_restart_limit():
+    """Restart lengths 1..SBM_MAX_RESTART are accepted, longer ones rejected
+    before anything runs."""
+    from paper_2506_12899_amd.problem import Problem
+    dev = _gpu()
+    prob = workloads.problem("disk32_q1")
+    print("[parity] restart limit", flush=True)
+    pb = Problem(prob.geometry, prob.n, prob.p, device=0, coarse_dofs=256)
+    b = pb.rhs(prob.solution.f, prob.solution.u)
+    x, st = pb.solve(b, tol=1e-8, restart=256)
+    assert st["converged"]
+    from paper_2506_12899_amd.native import SbmError
+    with pytest.raises(SbmError):
+        pb.solve(b, tol=1e-8, restart=257)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
 def test_solve_one_level_exact_preconditioner(fp32):
     """One level: the V-cycle is the dense inverse, A z = v lies in the basis
     already, and the first step ends FGMRES (the Gram-Schmidt second pass and
