@@ -216,8 +216,9 @@ int sbm_vcycle(struct sbm_problem *pb, const void *r_dev, void *z_dev, int fp32)
 
 /* Solve A x = b with FGMRES(restart), right-preconditioned by one V-cycle
  * (FP32 if o->vcycle_fp32), FP64 Arnoldi (classical Gram-Schmidt, second pass
- * only when the first cancels, |w'| < 0.1 |w|, when tol < 1e-10, or for basis
- * vectors beyond the 30th), x0 = 0; stops when the TRUE
+ * only when the first cancels, |w'| < 0.1 |w|, when tol < 1e-10, or beyond
+ * the 30th basis vector once the residual has fallen 1.6e4-fold within the
+ * cycle), x0 = 0; stops when the TRUE
  * relative residual ||b - A x|| / ||b|| <= tol, or after max_iter
  * iterations (then SBM_NOT_CONVERGED, x holds the last iterate).  b, x: FP64
  * device vectors; restart in 1..SBM_MAX_RESTART (else SBM_EINVAL); the

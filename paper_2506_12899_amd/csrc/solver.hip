@@ -1431,14 +1431,20 @@ static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, i
             // 1e-12: 33 iterations against 18 with the norm measured), so
             // there every step takes the second pass and measures |w''|.
             // The one-pass step's loss of orthogonality compounds along the
-            // basis (about eps times the square of the residual reduction
-            // within the cycle): harmless over 30 vectors, but on a weakly
-            // preconditioned 2D disk the basis drifts 1e-6 from orthogonal by
-            // vector 40 and 0.16 by vector 80, and the residual estimate then
-            // stalls (FGMRES(100): 100 iterations against 87).  Vectors beyond
-            // the 30th therefore always take the second pass.
+            // basis: classical Gram-Schmidt loses about eps kappa^2 (Giraud,
+            // Langou and Rozloznik, 2005), and the condition of the Arnoldi
+            // basis grows like the residual reduction R = beta / |g_j| within
+            // the cycle (Greenbaum, Rozloznik and Strakos, 1997).  On a weakly
+            // preconditioned 2D disk (FGMRES(100)) one pass throughout drifts
+            // 1.4e-6 from orthogonal by vector 40 and 0.16 by vector 80 (R =
+            // 3e4, 2e7), and the residual estimate stalls: 100 iterations
+            // against 87.  The estimate stays sound while eps R^2 < 1e-3 / R,
+            // so beyond the 30th vector one pass is kept only for R < (1e-3 /
+            // eps)^(1/3) = 1.6e4 (87 iterations there; basis loss 4e-7).
+            // Bases of up to 30 vectors keep the one-pass test alone.
             constexpr double eta = 0.1;
             constexpr int one_pass_max = 30;
+            constexpr double one_pass_reduction = 1.6e4;
             const bool norm_identity = tol >= 1e-10;
             const int nv = j + 1;
             double *vnext = V + (size_t)(j + 1) * n;
@@ -1450,7 +1456,8 @@ static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, i
             const double wsq = hp[nv];
             if (!std::isfinite(wsq) || !std::isfinite(h1sq)) return SBM_ENONFINITE;
             double hn;
-            if (norm_identity && nv <= one_pass_max && wsq - h1sq >= eta * eta * wsq) {
+            const bool one_pass_ok = nv <= one_pass_max || one_pass_reduction * std::fabs(gv[j]) > beta;
+            if (norm_identity && one_pass_ok && wsq - h1sq >= eta * eta * wsq) {
                 for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hp[i];
                 hn = std::sqrt(wsq - h1sq);
                 if ((rc = gs_subtract_scale(pb, n, nv, V, hd + HD_P1, hn > 0.0 ? 1.0 / hn : 1.0, w, vnext, s)))
