@@ -692,11 +692,12 @@ union FusedLds {
     FusedCellLds<P, T, OP> c;
 };
 
-// occupancy floor for the FP32 forms (5 waves per SIMD, both parts within
-// 102 VGPRs without a spill); the FP64 forms would spill
+// occupancy floor for the FP32 forms (Q3: 6 waves per SIMD, the LDS limit of
+// its 4-wave blocks, both parts within 80 VGPRs without a spill; Q2: 5); the
+// FP64 forms would spill
 template <int P, typename T>
 constexpr int fused_min_waves() {
-    return sizeof(T) == 4 ? 5 : 1;
+    return sizeof(T) == 4 ? (P == 3 ? 6 : 5) : 1;
 }
 
 template <int P, typename T, int OP, int EMIT>
