@@ -1538,6 +1538,36 @@ int launch_fill(long long n, T *x, T v, hipStream_t st) {
 template int launch_fill<double>(long long, double *, double, hipStream_t);
 template int launch_fill<float>(long long, float *, float, hipStream_t);
 
+// x[0..n) = y[0..n) = 0 in one launch, 16-byte stores (x and y 16-byte
+// aligned; the last n % (16 / sizeof(T)) entries one at a time)
+template <typename T>
+__global__ void zero2_kernel(long long n, T *__restrict__ x, T *__restrict__ y) {
+    constexpr int W = 16 / sizeof(T);
+    const long long nv = n / W;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (long long i = t0; i < nv; i += st) {
+        reinterpret_cast<float4 *>(x)[i] = z4;
+        if (y != nullptr) reinterpret_cast<float4 *>(y)[i] = z4;
+    }
+    for (long long i = nv * W + t0; i < n; i += st) {
+        x[i] = T(0);
+        if (y != nullptr) y[i] = T(0);
+    }
+}
+template <typename T>
+int launch_zero2(long long n, T *x, T *y, hipStream_t st) {
+    if (n <= 0) return 0;
+    if (((uintptr_t)x & 15) != 0 || ((uintptr_t)y & 15) != 0) return -1;
+    const long long nv = std::max<long long>(n / (16 / sizeof(T)), 1);
+    const int nb = (int)std::min<long long>((nv + 255) / 256, 8192);
+    hipLaunchKernelGGL((zero2_kernel<T>), dim3(nb), dim3(256), 0, st, n, x, y);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template int launch_zero2<double>(long long, double *, double *, hipStream_t);
+template int launch_zero2<float>(long long, float *, float *, hipStream_t);
+
 template <typename A, typename B>
 __global__ void cast_kernel(long long n, const A *__restrict__ x, B *__restrict__ y) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;

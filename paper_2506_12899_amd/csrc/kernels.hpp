@@ -141,6 +141,9 @@ int launch_coarse_solve_prolong(int d, int n, const double *A, const TX *x, TX *
                                 hipStream_t st);
 template <typename T>
 int launch_fill(long long n, T *x, T v, hipStream_t st);
+// x[0..n) = 0 and, if y is given, y[0..n) = 0 (one launch; x, y 16-byte aligned)
+template <typename T>
+int launch_zero2(long long n, T *x, T *y, hipStream_t st);
 // Additive (block-Jacobi) update of every active cell of a level:
 // d_K = alpha d_K + beta B_K r_K (alpha = 0: d is not read), then z_K += d_K
 // when z is given.  B_K: the cell's (transposed) inverse.

@@ -425,8 +425,7 @@ int resid_restrict(sbm_problem *pb, int l, const T *z, const T *b, T *bc, T *zc 
         // colour 0 of bc (and of the zero start) is zero; colour 1: boundary
         // cells by the cell kernel on its list, interior cells by the pencil kernel
         const long long n0 = (long long)Dc.n_col0 * Dc.nc;
-        KCHK(launch_fill<T>(n0, bc, T(0), pb->stream));
-        if (zc != nullptr) KCHK(launch_fill<T>(n0, zc, T(0), pb->stream));
+        KCHK(launch_zero2<T>(n0, bc, zc, pb->stream));
         ZeroStartArgs<T> zb = zs;
         zb.grp_bnd = Df.bl_cbnd != nullptr ? Df.bl_cbnd + Df.n_bl0 : nullptr;
         if (Df.n_bl1 > 0)
