@@ -267,7 +267,7 @@ def learned_leg(pb, prob, b, x, torch, args, t32, st32):
     return {"fp32_learned_s": tl, "iterations": st["iterations"], "converged": bool(st["converged"]),
             "rel_residual": st["rel_residual"], "judge_keeps": "learned" if better else "plain",
             "kept_s": tl if better else t32, "train_s": train_s, "train_samples": int(data[0].shape[0]),
-            "loss_first": hist[0], "loss_last": hist[-1]}
+            "loss_first": hist[0], "loss_last": hist[-1]}, net
 
 
 def main():
@@ -410,8 +410,9 @@ def main():
     out["smoother_block_gflops"] = blk_flops / ts32 / 1e9
     out["smoother_block_util_vs_fp32_valu"] = blk_flops / ts32 / 78.6e12
     out["smoother_block_util_vs_fp32_mfma"] = blk_flops / ts32 / 157.3e12
+    net = None
     if not args.no_learned and prob.dim == 3 and prob.p == 3:
-        out["learned"] = learned_leg(pb, prob, b, x, torch, args, t32, st32)
+        out["learned"], net = learned_leg(pb, prob, b, x, torch, args, t32, st32)
     extra = {}
     for name in [w for w in args.extra.split(",") if w and w != prob.name]:
         pe = workloads.problem(name)
@@ -438,6 +439,25 @@ def main():
             rec[f"{key}_rel_residual"] = ste["rel_residual"]
             rec[f"{key}_iterations"] = ste["iterations"]
             rec[f"{key}_converged"] = bool(ste["converged"])
+        if net is not None and pe.dim == 3 and pe.p == 3:
+            # the network trained above, installed on this problem: FP32 +
+            # learned against the plain FP32 solve, one timed solve
+            from paper_2506_12899_amd import learned
+            learned.install(pbe, net)
+            pbe.set_vcycle_fp32(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, stl = pbe.solve(be, xe, tol=1e-8, restart=pe.restart, max_iter=max_iter_e)
+            torch.cuda.synchronize()
+            tl = time.perf_counter() - t0
+            better = stl["converged"] and (not rec["fp32_converged"] or stl["iterations"] < rec["fp32_iterations"])
+            learned.use(pbe, False)
+            rec["learned"] = {"fp32_learned_s": tl, "iterations": stl["iterations"],
+                              "converged": bool(stl["converged"]), "rel_residual": stl["rel_residual"],
+                              "judge_keeps": "learned" if better else "plain"}
+            print(f"[bench] extra {name} FP32 + learned: {tl * 1e3:.2f} ms, {stl['iterations']} its, "
+                  f"rel {stl['rel_residual']:.2e}; judge keeps {'learned' if better else 'plain'}",
+                  file=sys.stderr, flush=True)
         extra[name] = rec
         print(f"[bench] extra {name}: FP32 {rec['fp32_s'] * 1e3:.2f} ms, FP64 {rec['fp64_s'] * 1e3:.2f} ms",
               file=sys.stderr, flush=True)

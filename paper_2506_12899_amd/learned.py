@@ -256,7 +256,7 @@ def use(pb, on):
     N.check(N.lib().sbm_use_learned(pb._h, int(bool(on))), pb._h)
 
 
-def judged_solve(pb, mlp, b, x=None, tol=1e-8, max_iter=300):
+def judged_solve(pb, mlp, b, x=None, tol=1e-8, max_iter=300, restart=30):
     """Solve with and without the learned correction and keep the better run.
 
     The plain smoother is the fallback and the judge: the learned form wins
@@ -264,9 +264,9 @@ def judged_solve(pb, mlp, b, x=None, tol=1e-8, max_iter=300):
     lower true residual.  The winner stays enabled on pb.  Returns
     (x, stats, choice) with choice "learned" or "plain" and stats of both."""
     use(pb, False)
-    x0, st0 = pb.solve(b, None, tol=tol, max_iter=max_iter)
+    x0, st0 = pb.solve(b, None, tol=tol, restart=restart, max_iter=max_iter)
     install(pb, mlp)
-    x1, st1 = pb.solve(b, None, tol=tol, max_iter=max_iter)
+    x1, st1 = pb.solve(b, None, tol=tol, restart=restart, max_iter=max_iter)
     if st1["converged"] != st0["converged"]:
         better = st1["converged"]
     elif st0["converged"]:
