@@ -1555,7 +1555,11 @@ static int solve_body(sbm_problem *pb, const double *b, double *x, double tol, i
 // (host containers throw std::bad_alloc; nothing may leave through the C ABI)
 int sbm_solve(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st) {
     try {
-        if (!pb || pb->host_only || m < 1 || m > MAX_RESTART) return SBM_EINVAL;
+        if (!pb || pb->host_only) return SBM_EINVAL;
+        if (m < 1 || m > MAX_RESTART) {
+            pb->last_error = "restart length " + std::to_string(m) + " outside 1.." + std::to_string(MAX_RESTART);
+            return SBM_EINVAL;
+        }
         const HostLevel &L = pb->levels.back();
         const long long n = (long long)L.n_act * L.nc;
         int rc;
@@ -1632,7 +1636,11 @@ long long sbm_solve_noalloc_doubles(const sbm_problem *pb, int m) {
 
 int sbm_solve_noalloc(sbm_problem *pb, const double *b, double *x, double tol, int m, int max_iter, sbm_stats *st) {
     try {
-        if (!pb || pb->host_only || m < 1 || m > MAX_RESTART) return SBM_EINVAL;
+        if (!pb || pb->host_only) return SBM_EINVAL;
+        if (m < 1 || m > MAX_RESTART) {
+            pb->last_error = "restart length " + std::to_string(m) + " outside 1.." + std::to_string(MAX_RESTART);
+            return SBM_EINVAL;
+        }
         const long long need = sbm_solve_noalloc_doubles(pb, m);
         const long long cap = (long long)(SBM_NOALLOC_SCRATCH_BYTES / sizeof(double));
         if (need > cap) {

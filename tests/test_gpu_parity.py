@@ -387,8 +387,10 @@ def test_solve_restart_limit():
     x, st = pb.solve(b, tol=1e-8, restart=256)
     assert st["converged"]
     from paper_2506_12899_amd.native import SbmError
-    with pytest.raises(SbmError):
+    with pytest.raises(SbmError, match="restart length 257"):
         pb.solve(b, tol=1e-8, restart=257)
+    with pytest.raises(SbmError, match="restart length 0"):
+        pb.solve(b, tol=1e-8, restart=0, noalloc=True)
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
