@@ -782,6 +782,9 @@ int launch_fused(int d, int p, int op, int nbnd, const int *bcells, int npen, co
 template int launch_fused<float>(int, int, int, int, const int *, int, const int *, const float *, float *,
                                  const float *, const CellArgs<float> &, const KRef<float> &, hipStream_t,
                                  const EmitArgs<float> *);
+template int launch_fused<double>(int, int, int, int, const int *, int, const int *, const double *, double *,
+                                 const double *, const CellArgs<double> &, const KRef<double> &, hipStream_t,
+                                 const EmitArgs<double> *);
 
 // Residual and restriction in one launch (Sec. 3.2: the restriction is the
 // transpose of the embedding); the residual is not written to memory.

@@ -84,7 +84,7 @@ int launch_pencil(int d, int p, int op, int ncells, const int *cells, const T *x
                   const CellArgs<T> &a, const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e);
 // the boundary cells (bcells, one thread per DoF) and the interior cells
 // (pcells, pencil form) of a 3D Q2/Q3 level in one launch: OP_APPLY, OP_RESID
-// or OP_SMOOTH (e: null or EMIT_F64); instantiated for FP32
+// or OP_SMOOTH (e: null, or EMIT_F64 in FP32 only); FP32 and FP64
 template <typename T>
 int launch_fused(int d, int p, int op, int nbnd, const int *bcells, int npen, const int *pcells, const T *x, T *y,
                  const T *b, const CellArgs<T> &a, const KRef<T> &R, hipStream_t st, const EmitArgs<T> *e);

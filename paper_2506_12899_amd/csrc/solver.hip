@@ -304,10 +304,11 @@ int level_apply(sbm_problem *pb, int l, int op, const T *x, T *y, const T *b) {
     CellArgs<T> a = cell_args(D, false);
     if (D.pencil) {
         // boundary cells one thread per DoF, interior cells in the pencil form
-        // (disjoint outputs): FP32 in one launch, FP64 in two (measured on
-        // the 96^3 Q3 sphere: the one-launch FP64 apply takes 131 us against
-        // 125 us, its register budget the larger of the two kernels')
-        if constexpr (sizeof(T) == 4) {
+        // (disjoint outputs): in one launch, except the FP64 Q3 operator (its
+        // one-launch form measured 137.7 against 134.7 us on the 96^3 sphere,
+        // the register budget the larger of the two kernels'; on the 64^3 Q2
+        // sphere the FP64 one-launch apply takes 22.0 against 23.9 us)
+        if (sizeof(T) == 4 || D.p == 2) {
             KCHK(launch_fused<T>(D.d, D.p, op, D.n_bl0 + D.n_bl1, D.bnd_list, D.n_int0 + D.n_int1, D.pen_all, x, y, b,
                                  a, D.kref, pb->stream, nullptr));
         } else {
@@ -337,15 +338,10 @@ int colour_update(sbm_problem *pb, int l, int colour, const T *b, T *z, const Em
         CellArgs<T> a = cell_args(D, learned);
         const int nb = colour == 0 ? D.n_bl0 : D.n_bl1, ni = colour == 0 ? D.n_int0 : D.n_int1;
         const int *bl = D.bnd_list + (colour == 0 ? 0 : D.n_bl0), *il = D.pen_col + (colour == 0 ? 0 : D.n_int0);
-        if constexpr (sizeof(T) == 4) {
-            // one launch (64^3 Q2 sphere FP32 solve 6.06 -> 5.44 ms, 96^3 Q3 sphere 86.0 -> 84.7 ms)
-            KCHK(launch_fused<T>(D.d, D.p, OP_SMOOTH, nb, bl, ni, il, z, z, b, a, D.kref, pb->stream, em));
-        } else {
-            a.perm = bl;
-            KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, 0, nb, z, z, b, a, D.kref, pb->stream, em));
-            a.perm = nullptr;
-            KCHK(launch_pencil<T>(D.d, D.p, OP_SMOOTH, ni, il, z, z, b, a, D.kref, pb->stream, em));
-        }
+        // one launch (FP32: 64^3 Q2 sphere solve 6.06 -> 5.44 ms, 96^3 Q3
+        // sphere 86.0 -> 84.7 ms; FP64: 96^3 Q3 sphere solve 120.6 -> 117.0 ms,
+        // 64^3 Q2 7.46 -> 7.31 ms)
+        KCHK(launch_fused<T>(D.d, D.p, OP_SMOOTH, nb, bl, ni, il, z, z, b, a, D.kref, pb->stream, em));
         return SBM_OK;
     }
     KCHK(launch_cellop<T>(D.d, D.p, OP_SMOOTH, c0, nc, z, z, b, cell_args(D, learned), D.kref, pb->stream, em));
