@@ -9,7 +9,8 @@ with the problem already set up and b already resident in HBM.  The timed
 form is the production one (FP32 V-cycle inside FP64 FGMRES); the plain FP64
 solve is timed the same way beside it.  The default workload is the 96^3 Q3
 sphere in its stabilised form (see paper_2506_12899_amd/workloads.py); the 2D
-Q2 star's and the 128^3 Q3 union's solve times (the latter with FGMRES(256))
+Q2 star's, the 64^3 Q2 sphere's and the 128^3 Q3 union's solve times (the
+latter with FGMRES(256)), apply throughput and smoother block-product rate
 are added as extra keys.  The dominant kernel's roofline is
 measured live with HIP events on the library's stream, and the CPU oracle is
 timed on the host on the same problem.
@@ -276,7 +277,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere96_q3")
-    ap.add_argument("--extra", default="star512_q2,balls128_q3",
+    ap.add_argument("--extra", default="star512_q2,sphere64_q2,balls128_q3",
                     help="comma-separated workloads whose solve times are added as extra keys ('' for none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-learned", action="store_true",
@@ -439,6 +440,19 @@ def main():
             rec[f"{key}_rel_residual"] = ste["rel_residual"]
             rec[f"{key}_iterations"] = ste["iterations"]
             rec[f"{key}_converged"] = bool(ste["converged"])
+        # finest-level apply throughput and the colour update's block-product
+        # rate, as for the main workload
+        ta64e = time_apply(pbe, torch, False, 100)
+        ta32e = time_apply(pbe, torch, True, 100)
+        ts32e = time_smooth(pbe, torch, True, 100)
+        rec["apply_mdofs_fp64"] = pbe.n_dofs / ta64e / 1e6
+        rec["apply_mdofs_fp32"] = pbe.n_dofs / ta32e / 1e6
+        rec["smooth_us_fp32"] = ts32e * 1e6
+        nce = (pe.p + 1) ** pe.dim
+        blk_e = 2.0 * nce * nce * pbe.layout.n_active / 2
+        rec["smoother_block_gflops"] = blk_e / ts32e / 1e9
+        rec["smoother_block_util_vs_fp32_valu"] = blk_e / ts32e / 78.6e12
+        rec["smoother_block_util_vs_fp32_mfma"] = blk_e / ts32e / 157.3e12
         if net is not None and pe.dim == 3 and pe.p == 3:
             # the network trained above, installed on this problem: FP32 +
             # learned against the plain FP32 solve, one timed solve
